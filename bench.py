@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the FLASH hot path on one MI355X: the approximate k-NN graph
+of a webspam-shaped synthetic set (350,000 rows, 16.6M columns, ~1.3G
+nonzeros; K=4, L=64, b=4, R=128, k=128).
+
+One step = the whole path over the batch, with the input already in HBM:
+DOPH hashing of every row, reservoir insertion into the L tables, and the
+count-based top-k query of every row against the index (itself left out).
+The same kernels flash_knn_graph launches are called phase by phase so that
+HIP events on the launch stream time each phase inside the timed region.
+
+Prints one JSON line (rank 0).  Extra keys: "roofline" (dominant kernel vs
+the 8 TB/s HBM peak), "cpu_baseline" (the CPU oracle on the host's cores),
+"phases" (per-phase times and algorithmic bytes).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+WORKLOADS = {
+    # name: (row recipe, K, L, b, R, k)
+    "webspam": ("WEBSPAM", 4, 64, 4, 128, 128),
+    "tiny": ("TINY", 4, 16, 4, 32, 16),
+    "url": ("URL", 5, 32, 3, 64, 64),
+}
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS))
+    ap.add_argument("--rows", type=int, default=0, help="override the row count (parity/debug only)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-queries", type=int, default=20000,
+                    help="queries the CPU oracle answers (the rest is extrapolated)")
+    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        log("multi-GPU runs are not part of this build (one GPU per box); rerun with --gpus 1")
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import datagen, flash
+
+    torch.cuda.set_device(0)
+    rec_name, K, L, b, R, k = WORKLOADS[args.workload]
+    spec = getattr(datagen, rec_name)
+    if args.rows:
+        spec = datagen.scaled(spec, args.rows)
+    n = spec.n_rows
+    t0 = time.time()
+    rp, ci = datagen.make_rows(spec, 1, device="cuda")
+    torch.cuda.synchronize()
+    nnz = int(ci.numel())
+    log(f"generated {args.workload}: {n} rows, {nnz} nnz ({nnz / n:.1f}/row) in {time.time() - t0:.1f}s")
+
+    p = flash.flash_params.make(K, L, b, R, seed=1)
+    M = p.M
+    counts, ids = flash.alloc_index(p)
+    keys = torch.empty(n * L, dtype=torch.int32, device="cuda")
+    ins_ws = flash.alloc_workspace(flash.OP_INSERT, p, n_rows=n)
+    q_ws = flash.alloc_workspace(flash.OP_QUERY_KEYS, p, n_queries=n, k=k)
+    self_ids = torch.arange(n, dtype=torch.int32, device="cuda")
+    oi = torch.empty(n * k, dtype=torch.int32, device="cuda")
+    oc = torch.empty(n * k, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def step(ev):
+        ev[0].record(stream)
+        flash.flash_hash(p, rp, ci, keys, stream=stream)
+        ev[1].record(stream)
+        flash.flash_insert_keys(p, keys, counts, ids, ins_ws, stream=stream)
+        ev[2].record(stream)
+        flash.flash_query_keys(p, counts, ids, n, keys, k, oi, oc, q_ws, self_ids=self_ids,
+                               stream=stream)
+        ev[3].record(stream)
+
+    evs = [[torch.cuda.Event(enable_timing=True) for _ in range(4)] for _ in range(args.steps)]
+    warm = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    for _ in range(args.warmup):
+        step(warm)
+    torch.cuda.synchronize()
+    log("warmup done")
+    w0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - w0
+    phase_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])
+    step_ms = float(np.mean([e[0].elapsed_time(e[3]) for e in evs]))
+    ph = phase_ms.mean(axis=0)
+    log(f"steps done: {step_ms:.3f} ms/step (wall {1e3 * wall / args.steps:.3f}); "
+        f"hash {ph[0]:.3f} insert {ph[1]:.3f} query {ph[2]:.3f} ms")
+
+    # algorithmic bytes per launch
+    kq = keys.view(n, L).long()
+    cnt = counts.view(L, M).long()
+    occ = torch.clamp(cnt[torch.arange(L, device="cuda")[None, :], kq.clamp(0, M - 1)], max=R)
+    occ = torch.where(kq >= 0, occ, torch.zeros_like(occ)) if kq.min() < 0 else occ
+    occ_sum = int(occ.sum().item())
+    bytes_hash = 4 * nnz + 8 * (n + 1) + 4 * n * L
+    n_ins = n * L
+    nb = L * M
+    bytes_insert = (4 * n_ins * 2 + 4 * n_ins * 3 + 4 * n_ins + 4 * nb * 4
+                    + 4 * int(torch.clamp(cnt, max=R).sum().item()))
+    bytes_query = 4 * n * L * 2 + 4 * occ_sum + 8 * n * k + 4 * n
+    phases = {
+        "hash": {"ms": round(float(ph[0]), 4), "alg_bytes": bytes_hash,
+                 "GBps": round(bytes_hash / (ph[0] * 1e6), 1)},
+        "insert": {"ms": round(float(ph[1]), 4), "alg_bytes": bytes_insert,
+                   "GBps": round(bytes_insert / (ph[1] * 1e6), 1)},
+        "query": {"ms": round(float(ph[2]), 4), "alg_bytes": bytes_query,
+                  "GBps": round(bytes_query / (ph[2] * 1e6), 1),
+                  "occupied_ids_per_query": round(occ_sum / n, 1)},
+    }
+    dom = max(("hash", "query"), key=lambda x: phases[x]["ms"])
+    kernel = {"hash": "doph_hash_kernel", "query": "count_topk_kernel"}[dom]
+    achieved = phases[dom]["alg_bytes"] / (phases[dom]["ms"] * 1e6)
+    traffic = None
+    try:
+        with open(args.traffic_json) as f:
+            tj = json.load(f)
+        ent = tj.get(args.workload, {}).get(kernel)
+        if ent and ent.get("source_sha") == _kernel_source_sha():
+            traffic = ent["bytes_per_launch"]
+    except (OSError, ValueError):
+        pass
+    roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(rp, ci, K, L, b, R, k, n, args.cpu_queries)
+
+    out = {
+        "metric": "k-NN graph build time + queries/s (webspam-shape)",
+        "value": round(n / (step_ms / 1e3), 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(step_ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}-shaped k-NN graph", "rows": n, "nnz": nnz,
+                   "K": K, "L": L, "bits_per_hash": b, "R": R, "k": k, "seed": 1},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "phases": phases,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _kernel_source_sha():
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1709_01190_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        if f.endswith((".hip", ".hpp", ".cpp")):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def cpu_baseline(rp, ci, K, L, b, R, k, n, q_sample):
+    """The CPU oracle (plain C + OpenMP) on the same arrays: hash and build of
+    all rows, then q_sample of the n queries; the query time is scaled to n."""
+    import numpy as np
+
+    import oracle
+
+    rph, cih = rp.cpu().numpy(), ci.cpu().numpy()
+    op = oracle.params(K, L, b, R, seed=1)
+    t0 = time.perf_counter()
+    keys = oracle.doph(op, rph, cih)
+    t1 = time.perf_counter()
+    counts, ids = oracle.build_tables(op, keys)
+    t2 = time.perf_counter()
+    qs = min(n, q_sample)
+    sel = np.arange(qs, dtype=np.int64)
+    oracle.query(op, counts, ids, keys[sel], k, self_ids=sel.astype(np.int32))
+    t3 = time.perf_counter()
+    total = (t1 - t0) + (t2 - t1) + (t3 - t2) * n / qs
+    log(f"cpu oracle: hash {t1 - t0:.2f}s build {t2 - t1:.2f}s query({qs}) {t3 - t2:.2f}s "
+        f"-> {total:.2f}s for the graph")
+    return {"value": round(n / total, 1), "unit": "queries/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"hash+build of all {n} rows, {qs} of {n} queries timed and scaled to {n}",
+            "seconds_graph": round(total, 3)}
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,169 @@
+/*
+ * flash.h — C ABI of the FLASH hot path for AMD Instinct MI355X (gfx950).
+ *
+ * FLASH (Wang, Shrivastava, Wang & Ryu, arXiv 1709.01190) answers k-nearest-
+ * neighbour queries over ultra-sparse binary rows with three data-parallel
+ * steps: densified one-permutation minwise hashing (paper Sec. 2.3), L hash
+ * tables of fixed-size reservoirs (Sec. 2.4, Sec. 3.2 item 2, Alg. 1-2) and
+ * count-based top-k selection over the L buckets a query hits (Sec. 3.2
+ * item 3, Alg. 3).
+ *
+ * Conventions for every entry point:
+ *  - All array pointers are DEVICE pointers (hipMalloc'd or torch CUDA
+ *    tensors) unless a comment says "host".  The caller owns every buffer;
+ *    the library never allocates device memory.  Scratch space is a
+ *    caller-provided workspace of at least flash_workspace_bytes() bytes,
+ *    256-byte aligned.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls only enqueue work and return; outputs are valid once the stream
+ *    has been synchronised.  Calls that share a workspace must be ordered on
+ *    one stream.
+ *  - Return value: FLASH_OK (0) or a negative FLASH_E* code.  On error nothing
+ *    has been enqueued (argument errors) or the HIP error is reported
+ *    (FLASH_EHIP); flash_last_error() gives a message for the calling thread.
+ *  - CSR input: row_ptr int64[n_rows + 1] and col_idx int32[nnz] with
+ *    nnz = row_ptr[n_rows] passed explicitly.  Columns are read as unsigned
+ *    32-bit ids; order inside a row is free and duplicates count once (binary
+ *    set semantics, Sec. 2.1); float values are not taken.  Row bounds are
+ *    clamped to [0, nnz] on the device, so a malformed row_ptr cannot read
+ *    outside col_idx (such a row is hashed as whatever lies in its clamped
+ *    range, possibly empty).
+ *  - Index layout (Sec. 3.5: memory O(L * R * Range)): counts uint32[L][M]
+ *    and ids int32[L][M][R] with M = 2^(K * bits_per_hash).  counts[t][m] is
+ *    the number of rows whose key in table t is m; slots
+ *    [0, min(counts[t][m], R)) of ids[t][m] hold the kept row ids in
+ *    ascending reservoir priority; later slots are not part of the index and
+ *    are never read.
+ */
+#ifndef FLASH_H
+#define FLASH_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define FLASH_API __attribute__((visibility("default")))
+#else
+#define FLASH_API
+#endif
+
+#define FLASH_OK 0
+#define FLASH_EINVAL (-1)   /* invalid argument or parameter */
+#define FLASH_ENOSPC (-2)   /* workspace (or an output) too small */
+#define FLASH_EHIP (-3)     /* HIP runtime / launch error */
+#define FLASH_ENOTIMPL (-4) /* parameters outside what the kernels support */
+
+/* Key of an empty row or query in every table (never inserted). */
+#define FLASH_EMPTY_KEY 0xFFFFFFFFu
+
+/* Method parameters (Sec. 2.2, Sec. 4.4.1).  Limits checked by every call:
+ * 1 <= K, 1 <= L <= 256, 1 <= bits_per_hash, K * bits_per_hash <= 30,
+ * K * L <= 4096 (DOPH bins), 1 <= R <= 1024, L * R <= 8192,
+ * 0 <= densify_attempts <= 65535, reserved == 0. */
+typedef struct flash_params {
+    int32_t K;                /* minhashes per table key (meta-hash width)      */
+    int32_t L;                /* number of hash tables                          */
+    int32_t bits_per_hash;    /* b: low bits of each minhash kept in a key      */
+    int32_t R;                /* reservoir capacity per bucket                  */
+    uint64_t seed;            /* expands to the permutation, densification and
+                                 reservoir-priority seeds                       */
+    int32_t densify_attempts; /* random probes per empty DOPH bin (default 64)  */
+    int32_t reserved;         /* must be 0                                      */
+} flash_params;
+
+/* Workspace users, for flash_workspace_bytes(). */
+#define FLASH_OP_HASH 0       /* flash_hash: needs none                          */
+#define FLASH_OP_INSERT 1     /* flash_insert_keys                               */
+#define FLASH_OP_BUILD 2      /* flash_build_index                               */
+#define FLASH_OP_QUERY_KEYS 3 /* flash_query_keys                                */
+#define FLASH_OP_QUERY 4      /* flash_query_batch                               */
+#define FLASH_OP_KNN_GRAPH 5  /* flash_knn_graph                                 */
+
+/* Host only.  0 if *p is within the limits above, else FLASH_EINVAL or
+ * FLASH_ENOTIMPL with a message in flash_last_error(). */
+FLASH_API int flash_check_params(const flash_params *p);
+
+/* Host only.  Element counts of the two index arrays: counts (L * M) and
+ * ids (L * M * R). */
+FLASH_API int flash_index_elems(const flash_params *p, uint64_t *counts_elems,
+                                uint64_t *ids_elems);
+
+/* Host only.  Workspace bytes needed by operation `op` for n_rows indexed rows
+ * (insert/build/graph) or n_queries queries (query ops) and k results per
+ * query.  Unused sizes may be 0. */
+FLASH_API int flash_workspace_bytes(int op, const flash_params *p, int64_t n_rows,
+                                    int64_t n_queries, int32_t k, size_t *bytes);
+
+/* Sec. 2.3 (DOPH) + Sec. 2.2 / Alg. 2 line 5 (MapKHashesToAddress).
+ * For each CSR row i: the K*L densified one-permutation minhashes and the L
+ * table keys keys[i][t] (uint32[n_rows][L], FLASH_EMPTY_KEY for an empty row).
+ * codes (uint32[n_rows][K*L]) is written only if not NULL. */
+FLASH_API int flash_hash(const flash_params *p, int64_t n_rows, int64_t nnz,
+                         const int64_t *row_ptr, const int32_t *col_idx, uint32_t *keys,
+                         uint32_t *codes, void *stream);
+
+/* Alg. 2 (adding phase) with Alg. 1's reservoir read as bottom-R priority
+ * sampling.  Clears counts, then adds row i (id i, 0 <= i < n_rows) to bucket
+ * keys[i][t] of every table t.  Keys that are FLASH_EMPTY_KEY or >= M are
+ * skipped.  Requires n_rows * L < 2^32 and n_rows < 2^31.  The tables are
+ * bit-identical for any launch order or configuration. */
+FLASH_API int flash_insert_keys(const flash_params *p, int64_t n_rows, const uint32_t *keys,
+                                uint32_t *counts, int32_t *ids, void *workspace,
+                                size_t workspace_bytes, void *stream);
+
+/* Adding phase from CSR: flash_hash, then flash_insert_keys.  The keys are
+ * written to keys_out (uint32[n_rows][L]) if it is not NULL, else kept in the
+ * workspace. */
+FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t nnz,
+                                const int64_t *row_ptr, const int32_t *col_idx,
+                                uint32_t *counts, int32_t *ids, uint32_t *keys_out,
+                                void *workspace, size_t workspace_bytes, void *stream);
+
+/* Alg. 3 (querying phase) from precomputed keys qkeys uint32[n_queries][L].
+ * cnt(x) = number of tables whose bucket qkeys[q][t] keeps id x; ids equal to
+ * self_ids[q] (if self_ids is not NULL and the entry is >= 0) are left out.
+ * out_ids / out_counts (int32[n_queries][k]) get the first k ids by (cnt
+ * descending, id ascending), padded with id -1, count 0.  Requires
+ * 1 <= k <= 1024 and fewer than 2^32 / 2^ceil(log2(L+2)) indexed rows. */
+FLASH_API int flash_query_keys(const flash_params *p, const uint32_t *counts, const int32_t *ids,
+                               int64_t n_indexed, int64_t n_queries, const uint32_t *qkeys,
+                               const int32_t *self_ids, int32_t k, int32_t *out_ids,
+                               int32_t *out_counts, void *workspace, size_t workspace_bytes,
+                               void *stream);
+
+/* Querying phase from CSR queries: flash_hash of the queries into the
+ * workspace, then flash_query_keys. */
+FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, const int32_t *ids,
+                                int64_t n_indexed, int64_t n_queries, int64_t nnz,
+                                const int64_t *q_row_ptr, const int32_t *q_col_idx,
+                                const int32_t *self_ids, int32_t k, int32_t *out_ids,
+                                int32_t *out_counts, void *workspace, size_t workspace_bytes,
+                                void *stream);
+
+/* Sec. 1 / Sec. 4.3: approximate k-NN graph.  Builds the index of all rows
+ * into counts/ids, then queries every row with its own keys, leaving the row
+ * itself out. */
+FLASH_API int flash_knn_graph(const flash_params *p, int64_t n_rows, int64_t nnz,
+                              const int64_t *row_ptr, const int32_t *col_idx, int32_t k,
+                              uint32_t *counts, int32_t *ids, int32_t *out_ids,
+                              int32_t *out_counts, void *workspace, size_t workspace_bytes,
+                              void *stream);
+
+/* Text for a FLASH_* code (static storage). */
+FLASH_API const char *flash_strerror(int code);
+
+/* Detail of the last error on the calling thread ("" if none). */
+FLASH_API const char *flash_last_error(void);
+
+/* Library version string. */
+FLASH_API const char *flash_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FLASH_H */

@@ -1,0 +1,201 @@
+// Densified one-permutation minwise hashing (paper Sec. 2.3) and the table
+// keys of Sec. 2.2 ("MapKHashesToAddress"), one wavefront per CSR row.
+//
+// Per row the wave
+//   1. streams the row's column ids from HBM with 16-byte loads (scalar head
+//      and tail for the unaligned ends), hashes each id with the permutation
+//      pi(i) = fmix32(i ^ s_h), and keeps the minimum per bin with an LDS
+//      atomic min; bins are the B equal slices of the permuted range;
+//   2. builds the occupancy bitmask with ballots (one 64-bit ballot per 64
+//      bins);
+//   3. fills every empty bin from an originally occupied one: up to A probes
+//      at bins given by fmix32(((j << 16) | a) ^ s_d), then the nearest
+//      occupied bin to the right (cyclic);
+//   4. writes the L keys (K low-b-bit fields each) and, if asked, the B codes.
+// HBM traffic per row: 4 B per nonzero + 16 B of row_ptr + 4 L B of keys
+// (+ 4 B bytes of codes).
+#include "launch.hpp"
+
+namespace flashk {
+
+namespace {
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+struct HashArgs {
+  const int64_t* row_ptr;
+  const int32_t* col_idx;
+  uint32_t* keys;
+  uint32_t* codes;
+  int64_t n_rows;
+  int64_t nnz;
+  uint32_t s_h, s_d;
+  int B, K, L, b, A;
+  uint32_t mask;
+  int shift;  // 32 - log2(B) when B is a power of two
+};
+
+template <bool POW2>
+__device__ __forceinline__ void add_column(const HashArgs& a, uint32_t col, uint32_t* mins,
+                                           uint32_t* top_bin) {
+  const uint32_t h = fmix32(col ^ a.s_h);
+  const uint32_t bin = POW2 ? (a.shift >= 32 ? 0u : (h >> a.shift)) : __umulhi(h, (uint32_t)a.B);
+  // exactly one column id maps to 0xFFFFFFFF; its bin is remembered so that
+  // occupancy never relies on a sentinel value
+  if (h == kEmpty) *top_bin = bin;
+  atomicMin(&mins[bin], h);
+}
+
+__device__ __forceinline__ bool occupied(const uint32_t* occw, uint32_t j) {
+  return (occw[j >> 5] >> (j & 31)) & 1u;
+}
+
+template <bool POW2>
+__global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
+  extern __shared__ uint32_t lds[];
+  uint32_t* mins = lds;              // [B]
+  uint32_t* occw = lds + a.B;        // [ceil(B / 32)]
+  __shared__ uint32_t top_bin;
+  const int lane = threadIdx.x;
+  const int B = a.B;
+  const int nwords = (B + 31) >> 5;
+  const uintptr_t mis = ((uintptr_t)a.col_idx >> 2) & 3;  // element misalignment vs 16 B
+
+  for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) {
+    int64_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
+    beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
+    end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
+
+    for (int j = lane; j < B; j += kWave) mins[j] = kEmpty;
+    if (lane == 0) top_bin = kEmpty;
+    __syncthreads();
+
+    if (beg == end) {  // empty row: all keys and codes are the empty marker
+      for (int t = lane; t < a.L; t += kWave) a.keys[row * a.L + t] = kEmpty;
+      if (a.codes)
+        for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = kEmpty;
+      __syncthreads();
+      continue;
+    }
+
+    // 1. bin minima.  a0/a1: first/last 16-byte aligned element positions.
+    int64_t a0 = beg + (int64_t)((4 - ((uint64_t)(beg + mis) & 3)) & 3);
+    int64_t a1 = end - (int64_t)((uint64_t)(end + mis) & 3);
+    if (a0 >= a1) {
+      a0 = end;
+      a1 = end;
+    }
+    {
+      const int64_t e = beg + lane;
+      if (e < a0) add_column<POW2>(a, (uint32_t)a.col_idx[e], mins, &top_bin);
+      const int64_t f = a1 + lane;
+      if (f < end) add_column<POW2>(a, (uint32_t)a.col_idx[f], mins, &top_bin);
+    }
+    const int64_t nvec = (a1 - a0) >> 2;
+    const u32x4* vp = reinterpret_cast<const u32x4*>(a.col_idx + a0);
+    constexpr int U = 4;
+    for (int64_t v = lane; v < nvec; v += (int64_t)kWave * U) {
+      u32x4 x[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t idx = v + (int64_t)kWave * u;
+        if (idx < nvec) x[u] = __builtin_nontemporal_load(vp + idx);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int64_t idx = v + (int64_t)kWave * u;
+        if (idx < nvec) {
+          add_column<POW2>(a, x[u].x, mins, &top_bin);
+          add_column<POW2>(a, x[u].y, mins, &top_bin);
+          add_column<POW2>(a, x[u].z, mins, &top_bin);
+          add_column<POW2>(a, x[u].w, mins, &top_bin);
+        }
+      }
+    }
+    __syncthreads();
+
+    // 2. occupancy bitmask
+    const uint32_t tb = top_bin;
+    for (int j0 = 0; j0 < B; j0 += kWave) {
+      const int j = j0 + lane;
+      const bool o = j < B && (mins[j] != kEmpty || (uint32_t)j == tb);
+      const uint64_t m = __ballot(o);
+      if (lane == 0) {
+        occw[j0 >> 5] = (uint32_t)m;
+        if ((j0 >> 5) + 1 < nwords) occw[(j0 >> 5) + 1] = (uint32_t)(m >> 32);
+      }
+    }
+    __syncthreads();
+
+    // 3. densification: only empty bins are written and only occupied bins
+    // are read, so bins can be filled in place.
+    for (int j = lane; j < B; j += kWave) {
+      if (occupied(occw, (uint32_t)j)) continue;
+      int src = -1;
+      for (int t = 1; t <= a.A; ++t) {
+        const uint32_t p = __umulhi(fmix32((((uint32_t)j << 16) | (uint32_t)t) ^ a.s_d), (uint32_t)B);
+        if (occupied(occw, p)) {
+          src = (int)p;
+          break;
+        }
+      }
+      if (src < 0) {  // nearest occupied bin to the right, cyclically
+        const uint32_t s0 = (uint32_t)(j + 1 == B ? 0 : j + 1);
+        uint32_t w = s0 >> 5;
+        uint32_t bits = occw[w] & (0xFFFFFFFFu << (s0 & 31));
+        while (bits == 0) {
+          w = (w + 1 == (uint32_t)nwords) ? 0 : w + 1;
+          bits = occw[w];
+        }
+        src = (int)(w * 32 + (uint32_t)(__ffs(bits) - 1));
+      }
+      mins[j] = mins[src];
+    }
+    __syncthreads();
+
+    // 4. keys (and codes)
+    for (int t = lane; t < a.L; t += kWave) {
+      uint32_t key = 0;
+      for (int j = 0; j < a.K; ++j) key |= (mins[t * a.K + j] & a.mask) << (a.b * j);
+      a.keys[row * a.L + t] = key;
+    }
+    if (a.codes)
+      for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = mins[j];
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, uint32_t* keys, uint32_t* codes,
+                            hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  HashArgs a;
+  a.row_ptr = row_ptr;
+  a.col_idx = col_idx;
+  a.keys = keys;
+  a.codes = codes;
+  a.n_rows = n_rows;
+  a.nnz = nnz;
+  a.s_h = c.seeds.s_h;
+  a.s_d = c.seeds.s_d;
+  a.B = c.B;
+  a.K = c.K;
+  a.L = c.L;
+  a.b = c.b;
+  a.A = c.A;
+  a.mask = c.mask;
+  const bool pow2 = (c.B & (c.B - 1)) == 0;
+  a.shift = pow2 ? 32 - (31 - __builtin_clz((unsigned)c.B)) : 0;
+  const size_t lds = sizeof(uint32_t) * ((size_t)c.B + (size_t)((c.B + 31) / 32));
+  const int64_t want = (int64_t)device_info().cus * 32;
+  const int grid = (int)(n_rows < want ? n_rows : want);
+  if (pow2)
+    hipLaunchKernelGGL(doph_hash_kernel<true>, dim3(grid), dim3(64), lds, s, a);
+  else
+    hipLaunchKernelGGL(doph_hash_kernel<false>, dim3(grid), dim3(64), lds, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace flashk

@@ -1,0 +1,285 @@
+// C ABI of the FLASH hot path: argument checks, workspace carving and kernel
+// launches on the caller's stream.  No device memory is allocated here.
+#include <hip/hip_runtime.h>
+
+#include <mutex>
+#include <string>
+
+#include "../../include/flash.h"
+#include "launch.hpp"
+
+namespace flashk {
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* where) {
+  return fail(FLASH_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+int make_cfg(const flash_params* p, Cfg* c) {
+  if (!p) return fail(FLASH_EINVAL, "params is NULL");
+  if (p->reserved != 0) return fail(FLASH_EINVAL, "params.reserved must be 0");
+  if (p->K < 1 || p->L < 1 || p->bits_per_hash < 1 || p->R < 1)
+    return fail(FLASH_EINVAL, "K, L, bits_per_hash and R must be >= 1");
+  if (p->L > 256) return fail(FLASH_ENOTIMPL, "L > 256 is not supported");
+  if ((int64_t)p->K * p->bits_per_hash > 30)
+    return fail(FLASH_EINVAL, "K * bits_per_hash must be <= 30");
+  if ((int64_t)p->K * p->L > 4096) return fail(FLASH_ENOTIMPL, "K * L > 4096 bins is not supported");
+  if (p->R > 1024) return fail(FLASH_ENOTIMPL, "R > 1024 is not supported");
+  if ((int64_t)p->L * p->R > 8192) return fail(FLASH_ENOTIMPL, "L * R > 8192 is not supported");
+  if (p->densify_attempts < 0 || p->densify_attempts > 65535)
+    return fail(FLASH_EINVAL, "densify_attempts must be in [0, 65535]");
+  c->K = p->K;
+  c->L = p->L;
+  c->b = p->bits_per_hash;
+  c->R = p->R;
+  c->B = p->K * p->L;
+  c->A = p->densify_attempts;
+  c->M = 1u << (p->K * p->bits_per_hash);
+  c->mask = (1u << p->bits_per_hash) - 1u;
+  c->seeds = expand_seed(p->seed);
+  return FLASH_OK;
+}
+
+int check_rows(const Cfg& c, int64_t n_rows, bool for_insert) {
+  if (n_rows < 0) return fail(FLASH_EINVAL, "n_rows must be >= 0");
+  if (for_insert) {
+    if (n_rows >= (int64_t)1 << 31) return fail(FLASH_EINVAL, "n_rows must be < 2^31");
+    if ((uint64_t)n_rows * (uint64_t)c.L >= (uint64_t)1 << 32)
+      return fail(FLASH_EINVAL, "n_rows * L must be < 2^32");
+  }
+  return FLASH_OK;
+}
+
+int check_csr(int64_t n_rows, int64_t nnz, const int64_t* row_ptr, const int32_t* col_idx) {
+  if (nnz < 0) return fail(FLASH_EINVAL, "nnz must be >= 0");
+  if (n_rows > 0 && !row_ptr) return fail(FLASH_EINVAL, "row_ptr is NULL");
+  if (nnz > 0 && !col_idx) return fail(FLASH_EINVAL, "col_idx is NULL");
+  return FLASH_OK;
+}
+
+int check_query(const Cfg& c, int64_t n_indexed, int64_t n_queries, int32_t k) {
+  if (n_queries < 0 || n_indexed < 0) return fail(FLASH_EINVAL, "sizes must be >= 0");
+  if (k < 1 || k > 1024) return fail(FLASH_EINVAL, "k must be in [1, 1024]");
+  const int cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
+  if (n_indexed > ((int64_t)1 << (32 - cbits)))
+    return fail(FLASH_ENOTIMPL, "too many indexed rows for the packed (id, count) query table");
+  return FLASH_OK;
+}
+
+size_t keys_bytes(const Cfg& c, int64_t n) { return align256(4 * (uint64_t)n * (uint64_t)c.L); }
+
+}  // namespace
+
+const Device& device_info() {
+  static Device infos[64];
+  static bool have[64] = {};
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!have[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+      infos[dev].cus = cus;
+    have[dev] = true;
+  }
+  return infos[dev];
+}
+
+}  // namespace flashk
+
+using namespace flashk;
+
+extern "C" {
+
+FLASH_API int flash_check_params(const flash_params* p) {
+  Cfg c;
+  return make_cfg(p, &c);
+}
+
+FLASH_API int flash_index_elems(const flash_params* p, uint64_t* counts_elems, uint64_t* ids_elems) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if (counts_elems) *counts_elems = (uint64_t)c.L * c.M;
+  if (ids_elems) *ids_elems = (uint64_t)c.L * c.M * (uint64_t)c.R;
+  return FLASH_OK;
+}
+
+FLASH_API int flash_workspace_bytes(int op, const flash_params* p, int64_t n_rows, int64_t n_queries,
+                                    int32_t k, size_t* bytes) {
+  (void)k;
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if (!bytes) return fail(FLASH_EINVAL, "bytes is NULL");
+  if (n_rows < 0 || n_queries < 0) return fail(FLASH_EINVAL, "sizes must be >= 0");
+  size_t b = 0;
+  switch (op) {
+    case FLASH_OP_HASH: b = 0; break;
+    case FLASH_OP_INSERT: b = insert_ws_bytes(c, n_rows); break;
+    case FLASH_OP_BUILD: b = keys_bytes(c, n_rows) + insert_ws_bytes(c, n_rows); break;
+    case FLASH_OP_QUERY_KEYS: b = query_ws_bytes(c, n_queries); break;
+    case FLASH_OP_QUERY: b = keys_bytes(c, n_queries) + query_ws_bytes(c, n_queries); break;
+    case FLASH_OP_KNN_GRAPH: {
+      const size_t ins = insert_ws_bytes(c, n_rows), qry = query_ws_bytes(c, n_rows);
+      b = keys_bytes(c, n_rows) + (ins > qry ? ins : qry);
+      break;
+    }
+    default: return fail(FLASH_EINVAL, "unknown op");
+  }
+  *bytes = b;
+  return FLASH_OK;
+}
+
+FLASH_API int flash_hash(const flash_params* p, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col_idx, uint32_t* keys, uint32_t* codes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_rows(c, n_rows, false))) return r;
+  if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
+  if (n_rows > 0 && !keys) return fail(FLASH_EINVAL, "keys is NULL");
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, codes, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "doph_hash");
+}
+
+FLASH_API int flash_insert_keys(const flash_params* p, int64_t n_rows, const uint32_t* keys,
+                                uint32_t* counts, int32_t* ids, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_rows(c, n_rows, true))) return r;
+  if (!counts || !ids || (n_rows > 0 && !keys)) return fail(FLASH_EINVAL, "NULL array");
+  const size_t need = insert_ws_bytes(c, n_rows);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_INSERT)");
+  const InsertWs w = insert_ws_carve(c, n_rows, workspace);
+  hipError_t e = launch_insert(c, n_rows, keys, counts, ids, w, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
+}
+
+FLASH_API int flash_build_index(const flash_params* p, int64_t n_rows, int64_t nnz,
+                                const int64_t* row_ptr, const int32_t* col_idx, uint32_t* counts,
+                                int32_t* ids, uint32_t* keys_out, void* workspace,
+                                size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_rows(c, n_rows, true))) return r;
+  if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
+  if (!counts || !ids) return fail(FLASH_EINVAL, "NULL index array");
+  const size_t kb = keys_bytes(c, n_rows);
+  const size_t need = kb + insert_ws_bytes(c, n_rows);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_BUILD)");
+  uint32_t* keys = keys_out ? keys_out : (uint32_t*)workspace;
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  const InsertWs w = insert_ws_carve(c, n_rows, (char*)workspace + kb);
+  e = launch_insert(c, n_rows, keys, counts, ids, w, s);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
+}
+
+FLASH_API int flash_query_keys(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                               int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
+                               const int32_t* self_ids, int32_t k, int32_t* out_ids,
+                               int32_t* out_counts, void* workspace, size_t workspace_bytes,
+                               void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_query(c, n_indexed, n_queries, k))) return r;
+  if (n_queries > 0 && (!counts || !ids || !qkeys || !out_ids || !out_counts))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t need = query_ws_bytes(c, n_queries);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY_KEYS)");
+  const QueryWs w = query_ws_carve(c, n_queries, workspace);
+  hipError_t e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
+                              k, out_ids, out_counts, w, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                                int64_t n_indexed, int64_t n_queries, int64_t nnz,
+                                const int64_t* q_row_ptr, const int32_t* q_col_idx,
+                                const int32_t* self_ids, int32_t k, int32_t* out_ids,
+                                int32_t* out_counts, void* workspace, size_t workspace_bytes,
+                                void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_query(c, n_indexed, n_queries, k))) return r;
+  if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
+  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t kb = keys_bytes(c, n_queries);
+  const size_t need = kb + query_ws_bytes(c, n_queries);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY)");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* qkeys = (uint32_t*)workspace;
+  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
+  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k,
+                   out_ids, out_counts, w, s);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz,
+                              const int64_t* row_ptr, const int32_t* col_idx, int32_t k,
+                              uint32_t* counts, int32_t* ids, int32_t* out_ids, int32_t* out_counts,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_rows(c, n_rows, true))) return r;
+  if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
+  if ((r = check_query(c, n_rows, n_rows, k))) return r;
+  if (!counts || !ids || (n_rows > 0 && (!out_ids || !out_counts)))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t kb = keys_bytes(c, n_rows);
+  const size_t ins = insert_ws_bytes(c, n_rows), qry = query_ws_bytes(c, n_rows);
+  const size_t need = kb + (ins > qry ? ins : qry);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_KNN_GRAPH)");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* keys = (uint32_t*)workspace;
+  char* rest = (char*)workspace + kb;
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  e = launch_insert(c, n_rows, keys, counts, ids, insert_ws_carve(c, n_rows, rest), s);
+  if (e != hipSuccess) return hip_fail(e, "reservoir_insert");
+  e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, out_ids, out_counts,
+                   query_ws_carve(c, n_rows, rest), s);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API const char* flash_strerror(int code) {
+  switch (code) {
+    case FLASH_OK: return "ok";
+    case FLASH_EINVAL: return "invalid argument";
+    case FLASH_ENOSPC: return "workspace or output too small";
+    case FLASH_EHIP: return "HIP runtime error";
+    case FLASH_ENOTIMPL: return "parameters outside the supported range";
+    default: return "unknown error";
+  }
+}
+
+FLASH_API const char* flash_last_error(void) { return g_last_error.c_str(); }
+
+FLASH_API const char* flash_version(void) { return "flash-mi355x 0.1 (gfx950)"; }
+
+}  // extern "C"

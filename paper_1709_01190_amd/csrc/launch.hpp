@@ -1,0 +1,61 @@
+// Internal launch interface between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "flash_device.hpp"
+
+namespace flashk {
+
+// Derived, validated parameters shared by all launches.
+struct Cfg {
+  int K, L, b, R, B, A;
+  uint32_t M;      // buckets per table, 2^(K*b)
+  uint32_t mask;   // 2^b - 1
+  Seeds seeds;
+};
+
+struct Device {
+  int cus = 256;   // compute units of the current device
+};
+const Device& device_info();
+
+// ---- hash (doph_hash.hip)
+hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
+                            const int32_t* col_idx, uint32_t* keys, uint32_t* codes,
+                            hipStream_t s);
+
+// ---- insert (reservoir_insert.hip)
+struct InsertWs {
+  uint32_t* rank;       // [n_rows * L]   arrival rank inside its bucket
+  int32_t* staged;      // [n_rows * L]   ids grouped by bucket
+  uint32_t* seg;        // [L * M]        first staged slot of each bucket
+  uint32_t* tile_sums;  // [tiles + 1]    scan carries
+  uint32_t* worklist;   // [L * M]        buckets for the wave-level select
+  uint32_t* wl_len;     // [1]
+};
+size_t insert_ws_bytes(const Cfg& c, int64_t n_rows);
+InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws);
+hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t* counts,
+                         int32_t* ids, const InsertWs& w, hipStream_t s);
+
+// ---- query (count_topk.hip)
+struct QueryWs {
+  uint32_t* ovf_list;   // [n_queries]    queries whose candidates overflow the main table
+  uint32_t* ovf_len;    // [1]
+};
+size_t query_ws_bytes(const Cfg& c, int64_t n_queries);
+QueryWs query_ws_carve(const Cfg& c, int64_t n_queries, void* ws);
+// self_mode: 0 = none, 1 = self_ids array, 2 = query index is its own id
+hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
+                        int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
+                        const int32_t* self_ids, int self_mode, int32_t k, int32_t* out_ids,
+                        int32_t* out_counts, const QueryWs& w, hipStream_t s);
+
+// ---- misc
+hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace flashk

@@ -1,0 +1,231 @@
+"""Python binding of the FLASH C ABI (include/flash.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls and takes torch
+tensors that live on the GPU (their data pointers are passed through).  32-bit
+unsigned arrays (keys, codes, counts) are carried in int32 tensors, bit for bit.
+There is no CPU path: if ``libflash.so`` has not been built, loading fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libflash.so")
+
+FLASH_OK = 0
+FLASH_EINVAL = -1
+FLASH_ENOSPC = -2
+FLASH_EHIP = -3
+FLASH_ENOTIMPL = -4
+EMPTY_KEY = 0xFFFFFFFF
+
+OP_HASH, OP_INSERT, OP_BUILD, OP_QUERY_KEYS, OP_QUERY, OP_KNN_GRAPH = range(6)
+
+
+class FlashError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{msg} (code {code})")
+        self.code = code
+
+
+class flash_params(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_int32), ("L", ctypes.c_int32),
+                ("bits_per_hash", ctypes.c_int32), ("R", ctypes.c_int32),
+                ("seed", ctypes.c_uint64), ("densify_attempts", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, K, L, bits_per_hash, R, seed=1, densify_attempts=64):
+        return cls(K, L, bits_per_hash, R, seed, densify_attempts, 0)
+
+    @property
+    def M(self) -> int:
+        return 1 << (self.K * self.bits_per_hash)
+
+
+_lib = None
+_VP = ctypes.c_void_p
+_I64 = ctypes.c_int64
+
+
+def lib():
+    """Load libflash.so (raises if it is missing)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise FlashError(FLASH_EHIP, f"{LIB_PATH} is not built; run "
+                         "`python -m paper_1709_01190_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER(flash_params)
+    sig = {
+        "flash_check_params": [P],
+        "flash_index_elems": [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+        "flash_workspace_bytes": [ctypes.c_int, P, _I64, _I64, ctypes.c_int32,
+                                  ctypes.POINTER(ctypes.c_size_t)],
+        "flash_hash": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP],
+        "flash_insert_keys": [P, _I64, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_build_index": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_query_keys": [P, _VP, _VP, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP,
+                             ctypes.c_size_t, _VP],
+        "flash_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP,
+                              _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
+                            ctypes.c_size_t, _VP],
+    }
+    for name, args in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    for name in ("flash_strerror",):
+        getattr(L, name).argtypes = [ctypes.c_int]
+        getattr(L, name).restype = ctypes.c_char_p
+    for name in ("flash_last_error", "flash_version"):
+        getattr(L, name).argtypes = []
+        getattr(L, name).restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def _check(code: int):
+    if code != FLASH_OK:
+        L = lib()
+        raise FlashError(code, f"{L.flash_strerror(code).decode()}: {L.flash_last_error().decode()}")
+
+
+def _p(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("FLASH arrays must be GPU tensors")
+    if not t.is_contiguous():
+        raise ValueError("FLASH arrays must be contiguous")
+    return _VP(t.data_ptr())
+
+
+def _s(stream) -> _VP:
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return _VP(stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _need(t, numel, dtype, name):
+    if t is None:
+        return
+    if t.dtype not in dtype:
+        raise TypeError(f"{name}: dtype {t.dtype} not in {dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{name}: {t.numel()} elements, need {numel}")
+
+
+_U32 = (torch.int32, getattr(torch, "uint32", torch.int32))
+
+
+# ------------------------------------------------------------------ host-only calls
+
+def flash_check_params(p: flash_params) -> None:
+    _check(lib().flash_check_params(ctypes.byref(p)))
+
+
+def flash_index_elems(p: flash_params) -> Tuple[int, int]:
+    a, b = ctypes.c_uint64(), ctypes.c_uint64()
+    _check(lib().flash_index_elems(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def flash_workspace_bytes(op: int, p: flash_params, n_rows: int = 0, n_queries: int = 0,
+                          k: int = 0) -> int:
+    out = ctypes.c_size_t()
+    _check(lib().flash_workspace_bytes(op, ctypes.byref(p), n_rows, n_queries, k, ctypes.byref(out)))
+    return out.value
+
+
+def flash_version() -> str:
+    return lib().flash_version().decode()
+
+
+# ------------------------------------------------------------------ device calls
+
+def flash_hash(p, row_ptr, col_idx, keys, codes=None, stream=None):
+    n = row_ptr.numel() - 1
+    _need(row_ptr, n + 1, (torch.int64,), "row_ptr")
+    _need(col_idx, 0, (torch.int32,), "col_idx")
+    _need(keys, n * p.L, _U32, "keys")
+    _need(codes, n * p.K * p.L, _U32, "codes")
+    _check(lib().flash_hash(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx),
+                            _p(keys), _p(codes), _s(stream)))
+
+
+def flash_insert_keys(p, keys, counts, ids, workspace, stream=None):
+    n = keys.numel() // p.L
+    ce, ie = flash_index_elems(p)
+    _need(counts, ce, _U32, "counts")
+    _need(ids, ie, (torch.int32,), "ids")
+    _check(lib().flash_insert_keys(ctypes.byref(p), n, _p(keys), _p(counts), _p(ids),
+                                   _p(workspace), workspace.numel() * workspace.element_size(),
+                                   _s(stream)))
+
+
+def flash_build_index(p, row_ptr, col_idx, counts, ids, workspace, keys_out=None, stream=None):
+    n = row_ptr.numel() - 1
+    ce, ie = flash_index_elems(p)
+    _need(counts, ce, _U32, "counts")
+    _need(ids, ie, (torch.int32,), "ids")
+    _need(keys_out, n * p.L, _U32, "keys_out")
+    _check(lib().flash_build_index(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx),
+                                   _p(counts), _p(ids), _p(keys_out), _p(workspace),
+                                   workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_query_keys(p, counts, ids, n_indexed, qkeys, k, out_ids, out_counts, workspace,
+                     self_ids=None, stream=None):
+    q = qkeys.numel() // p.L
+    _need(out_ids, q * k, (torch.int32,), "out_ids")
+    _need(out_counts, q * k, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    _check(lib().flash_query_keys(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q, _p(qkeys),
+                                  _p(self_ids), k, _p(out_ids), _p(out_counts), _p(workspace),
+                                  workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
+                      workspace, self_ids=None, stream=None):
+    q = q_row_ptr.numel() - 1
+    _need(out_ids, q * k, (torch.int32,), "out_ids")
+    _need(out_counts, q * k, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    _check(lib().flash_query_batch(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+                                   q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx), _p(self_ids),
+                                   k, _p(out_ids), _p(out_counts), _p(workspace),
+                                   workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_knn_graph(p, row_ptr, col_idx, k, counts, ids, out_ids, out_counts, workspace,
+                    stream=None):
+    n = row_ptr.numel() - 1
+    ce, ie = flash_index_elems(p)
+    _need(counts, ce, _U32, "counts")
+    _need(ids, ie, (torch.int32,), "ids")
+    _need(out_ids, n * k, (torch.int32,), "out_ids")
+    _need(out_counts, n * k, (torch.int32,), "out_counts")
+    _check(lib().flash_knn_graph(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx), k,
+                                 _p(counts), _p(ids), _p(out_ids), _p(out_counts), _p(workspace),
+                                 workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+# ------------------------------------------------------------------ allocation helpers
+
+def alloc_index(p: flash_params, device="cuda"):
+    """(counts int32[L*M], ids int32[L*M*R]) tensors, uninitialised."""
+    ce, ie = flash_index_elems(p)
+    return (torch.empty(ce, dtype=torch.int32, device=device),
+            torch.empty(ie, dtype=torch.int32, device=device))
+
+
+def alloc_workspace(op: int, p: flash_params, n_rows=0, n_queries=0, k=0, device="cuda"):
+    nbytes = flash_workspace_bytes(op, p, n_rows, n_queries, k)
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)

@@ -1,0 +1,389 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Integer work, so every comparison is bit-exact: keys, codes, bucket counts,
+the occupied reservoir slots and the (id, count) k-NN lists.  Slots past a
+bucket's occupancy are not part of the index and are not compared.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+EMPTY = 0xFFFFFFFF
+
+
+def say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def fl():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1709_01190_amd import flash
+    flash.lib()
+    return flash
+
+
+def u32(t):
+    return t.detach().cpu().numpy().view(np.uint32)
+
+
+def i32(t):
+    return t.detach().cpu().numpy().view(np.int32)
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.view(dtype)
+    return t.cuda()
+
+
+def csr_from_rows(rows):
+    rp = np.zeros(len(rows) + 1, dtype=np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate([np.asarray(r, dtype=np.int64).astype(np.int32) for r in rows]) if rows \
+        else np.zeros(0, np.int32)
+    return rp, ci
+
+
+def fmix32_inverse(h):
+    h = np.asarray([h], dtype=np.uint32)
+
+    def unxorshift(v, s):
+        r = v.copy()
+        for _ in range(32 // s + 1):
+            r = v ^ (r >> np.uint32(s))
+        return r
+    h = unxorshift(h, 16)
+    h = h * np.uint32(pow(0xC2B2AE35, -1, 1 << 32))
+    h = unxorshift(h, 13)
+    h = h * np.uint32(pow(0x85EBCA6B, -1, 1 << 32))
+    h = unxorshift(h, 16)
+    return int(h[0])
+
+
+def occupied_equal(counts_a, ids_a, counts_b, ids_b, L, M, R):
+    """counts equal and the occupied slots of every bucket equal."""
+    ca = counts_a.reshape(L, M)
+    cb = counts_b.reshape(L, M)
+    assert np.array_equal(ca, cb), "bucket counts differ"
+    ia = ids_a.reshape(L, M, R)
+    ib = ids_b.reshape(L, M, R)
+    occ = np.minimum(ca, R)
+    slot = np.arange(R)[None, None, :]
+    mask = slot < occ[:, :, None]
+    assert np.array_equal(ia[mask], ib[mask]), "reservoir contents differ"
+
+
+def gpu_hash(fl, p, rp, ci, codes=True, offset=0):
+    import torch
+    n = rp.shape[0] - 1
+    buf = torch.zeros(ci.shape[0] + 8, dtype=torch.int32, device="cuda")
+    buf[offset:offset + ci.shape[0]] = dev(ci)
+    ci_d = buf[offset:offset + ci.shape[0]]
+    keys = torch.empty(n * p.L, dtype=torch.int32, device="cuda")
+    cod = torch.empty(n * p.K * p.L, dtype=torch.int32, device="cuda") if codes else None
+    fl.flash_hash(p, dev(rp), ci_d, keys, cod)
+    torch.cuda.synchronize()
+    return u32(keys).reshape(n, p.L), (u32(cod).reshape(n, p.K * p.L) if codes else None)
+
+
+def gpu_insert(fl, p, keys_np):
+    import torch
+    n = keys_np.shape[0]
+    counts, ids = fl.alloc_index(p)
+    ws = fl.alloc_workspace(fl.OP_INSERT, p, n_rows=n)
+    fl.flash_insert_keys(p, dev(keys_np.astype(np.uint32), torch.int32), counts, ids, ws)
+    torch.cuda.synchronize()
+    return counts, ids
+
+
+def gpu_query(fl, p, counts, ids, n_indexed, qkeys_np, k, self_ids=None):
+    import torch
+    q = qkeys_np.shape[0]
+    oi = torch.empty(q * k, dtype=torch.int32, device="cuda")
+    oc = torch.empty(q * k, dtype=torch.int32, device="cuda")
+    ws = fl.alloc_workspace(fl.OP_QUERY_KEYS, p, n_queries=q, k=k)
+    sd = dev(self_ids.astype(np.int32)) if self_ids is not None else None
+    fl.flash_query_keys(p, counts, ids, n_indexed, dev(qkeys_np.astype(np.uint32), torch.int32), k,
+                        oi, oc, ws, self_ids=sd)
+    torch.cuda.synchronize()
+    return i32(oi).reshape(q, k), i32(oc).reshape(q, k)
+
+
+# ------------------------------------------------------------------ hash
+
+def test_hash_tiny_workload(fl, orc):
+    from paper_1709_01190_amd import datagen
+    say("hash tiny 10k rows K4 L16 b4")
+    rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    keys, codes = gpu_hash(fl, p, rp, ci)
+    okeys, ocodes = orc.doph(orc.params(4, 16, 4, 32, seed=1), rp, ci, want_codes=True)
+    assert np.array_equal(codes, ocodes)
+    assert np.array_equal(keys, okeys)
+
+
+@pytest.mark.parametrize("K,L,b,A", [(4, 16, 4, 64), (5, 32, 3, 64), (1, 1, 16, 64), (16, 256, 1, 64),
+                                     (3, 3, 5, 0), (4, 64, 4, 2), (2, 70, 7, 64)])
+def test_hash_edge_rows(fl, orc, K, L, b, A):
+    say("hash edge rows", K, L, b, A)
+    rng = np.random.default_rng(K * 1000 + L)
+    seed = 77
+    s_h = orc.seeds(seed)[0]
+    top_col = fmix32_inverse(0xFFFFFFFF) ^ s_h  # the one column whose pi is 0xFFFFFFFF
+    top_col = top_col - (1 << 32) if top_col >= (1 << 31) else top_col
+    rows = [[], [5], [1, 2], list(range(63)), list(range(64)), list(range(65)),
+            rng.integers(-(1 << 31), (1 << 31) - 1, size=1000).tolist(),
+            [7, 7, 7, 3, 3, 9], rng.permutation(300).tolist(), [top_col], [top_col, 11, 12],
+            rng.integers(0, 1 << 20, size=5000).tolist(), [], [0]]
+    rp, ci = csr_from_rows(rows)
+    p = fl.flash_params.make(K, L, b, 8, seed=seed, densify_attempts=A)
+    okeys, ocodes = orc.doph(orc.params(K, L, b, 8, seed=seed, densify_attempts=A), rp, ci,
+                             want_codes=True)
+    for off in range(4):  # every 16-byte misalignment of the column array
+        keys, codes = gpu_hash(fl, p, rp, ci, offset=off)
+        assert np.array_equal(codes, ocodes), off
+        assert np.array_equal(keys, okeys), off
+
+
+def test_hash_malformed_row_pointers_stay_in_bounds(fl, orc):
+    say("hash malformed row_ptr")
+    import torch
+    ci = np.arange(100, dtype=np.int32)
+    rp = np.array([0, 10, 5, 200, -3, 100], dtype=np.int64)  # decreasing, past nnz, negative
+    p = fl.flash_params.make(4, 16, 4, 8)
+    keys = torch.empty(5 * 16, dtype=torch.int32, device="cuda")
+    fl.flash_hash(p, dev(rp), dev(ci), keys)
+    torch.cuda.synchronize()
+    k = u32(keys).reshape(5, 16)
+    # clamped rows: [0,10), [10,10) empty, [5,100), [100,100) empty, [0,100)
+    want_rows = [ci[0:10], ci[0:0], ci[5:100], ci[0:0], ci[0:100]]
+    wrp, wci = csr_from_rows(want_rows)
+    assert np.array_equal(k, orc.doph(orc.params(4, 16, 4, 8), wrp, wci))
+
+
+# ------------------------------------------------------------------ insert
+
+def test_insert_tiny_workload(fl, orc):
+    from paper_1709_01190_amd import datagen
+    say("insert tiny")
+    rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    op = orc.params(4, 16, 4, 32, seed=1)
+    keys = orc.doph(op, rp, ci)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    counts, ids = gpu_insert(fl, p, keys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
+
+
+@pytest.mark.parametrize("R", [1, 4, 32, 256, 1024])
+def test_insert_heavy_buckets(fl, orc, R):
+    # bucket sizes around every path switch: one thread (<= 8), a wave
+    # sorting all arrivals, and the priority-threshold select
+    say("insert heavy buckets R", R)
+    rng = np.random.default_rng(R)
+    K, L, b = 2, 3, 5
+    M = 1 << (K * b)
+    sizes = [0, 1, 7, 8, 9, 63, 64, 65, R - 1, R, R + 1, 2 * R, 2 * R + 1, 3 * R, 2047, 2049, 5000,
+             40000, 120000]
+    sizes = [s for s in sizes if s >= 0]
+    keys = []
+    for t in range(L):
+        col = np.concatenate([np.full(s, (i * 7 + t) % M, dtype=np.uint32) for i, s in enumerate(sizes)])
+        rng.shuffle(col)
+        keys.append(col)
+    n = max(len(c) for c in keys)
+    km = np.full((n, L), EMPTY, dtype=np.uint32)
+    for t in range(L):
+        km[:len(keys[t]), t] = keys[t]
+    km[rng.random((n, L)) < 0.01] = M + 5  # out-of-range keys are skipped like empty ones
+    op = orc.params(K, L, b, R, seed=R + 3)
+    ocounts, oids = orc.build_tables(op, km)
+    p = fl.flash_params.make(K, L, b, R, seed=R + 3)
+    counts, ids = gpu_insert(fl, p, km)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+
+
+def test_insert_is_deterministic(fl):
+    import torch
+    say("insert determinism")
+    rng = np.random.default_rng(5)
+    K, L, b, R = 3, 8, 3, 16
+    M = 1 << (K * b)
+    keys = (rng.zipf(1.3, size=(200000, L)) % M).astype(np.uint32)
+    p = fl.flash_params.make(K, L, b, R, seed=9)
+    c1, i1 = gpu_insert(fl, p, keys)
+    c2, i2 = gpu_insert(fl, p, keys)
+    occupied_equal(u32(c1), i32(i1), u32(c2), i32(i2), L, M, R)
+
+
+# ------------------------------------------------------------------ query
+
+@pytest.fixture(scope="module")
+def tiny_index(fl, orc):
+    from paper_1709_01190_amd import datagen
+    rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    op = orc.params(4, 16, 4, 32, seed=1)
+    keys = orc.doph(op, rp, ci)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    counts, ids = gpu_insert(fl, p, keys)
+    return p, op, rp, ci, keys, counts, ids, ocounts, oids
+
+
+@pytest.mark.parametrize("k", [1, 16, 100, 1024])
+def test_query_tiny_graph_mode(fl, orc, tiny_index, k):
+    say("query tiny graph k", k)
+    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    n = keys.shape[0]
+    self_ids = np.arange(n, dtype=np.int32)
+    oi, oc = gpu_query(fl, p, counts, ids, n, keys, k, self_ids)
+    wi, wc = orc.query(op, ocounts, oids, keys, k, self_ids=self_ids)
+    assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
+
+
+def test_query_mixed_keys_and_self(fl, orc, tiny_index):
+    say("query mixed keys")
+    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    rng = np.random.default_rng(8)
+    q = 3000
+    qk = keys[rng.integers(0, keys.shape[0], size=q)].copy()
+    mask = rng.random(qk.shape) < 0.2
+    qk[mask] = rng.integers(0, 1 << 16, size=int(mask.sum()))
+    qk[::17] = EMPTY
+    qk[5, 3] = (1 << 16) + 9  # out of range: ignored
+    self_ids = rng.integers(-1, keys.shape[0], size=q).astype(np.int32)
+    for sids in (None, self_ids):
+        oi, oc = gpu_query(fl, p, counts, ids, keys.shape[0], qk, 40, sids)
+        wi, wc = orc.query(op, ocounts, oids, qk, 40, self_ids=sids)
+        assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
+
+
+def test_query_overflow_table(fl, orc, monkeypatch):
+    # buckets far fuller than the first-pass table: every query takes the
+    # large-table launch; a second run with a table that fits checks both
+    say("query overflow")
+    rng = np.random.default_rng(9)
+    K, L, b, R = 1, 32, 2, 256
+    n = 6000
+    keys = rng.integers(0, 1 << (K * b), size=(n, L)).astype(np.uint32)
+    keys[:50] = rng.integers(0, 1 << (K * b), size=(50, L))
+    op = orc.params(K, L, b, R, seed=4)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(K, L, b, R, seed=4)
+    counts, ids = gpu_insert(fl, p, keys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
+    qk = keys[:700].copy()
+    qk[100:400, 4:] = EMPTY     # small queries stay in the first pass
+    wi, wc = orc.query(op, ocounts, oids, qk, 300, self_ids=np.arange(700, dtype=np.int32))
+    for cap in ("512", "2048", "16384"):
+        monkeypatch.setenv("FLASH_QUERY_CAP", cap)
+        oi, oc = gpu_query(fl, p, counts, ids, n, qk, 300, np.arange(700, dtype=np.int32))
+        assert np.array_equal(oi, wi) and np.array_equal(oc, wc), cap
+
+
+def test_query_many_tables(fl, orc):
+    say("query L=200")
+    rng = np.random.default_rng(10)
+    K, L, b, R = 2, 200, 4, 40
+    n = 3000
+    keys = rng.integers(0, 1 << (K * b), size=(n, L)).astype(np.uint32)
+    keys[1000:1100] = keys[0]  # one heavy cluster
+    op = orc.params(K, L, b, R, seed=6)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(K, L, b, R, seed=6)
+    counts, ids = gpu_insert(fl, p, keys)
+    wi, wc = orc.query(op, ocounts, oids, keys[:500], 64, self_ids=np.arange(500, dtype=np.int32))
+    oi, oc = gpu_query(fl, p, counts, ids, n, keys[:500], 64, np.arange(500, dtype=np.int32))
+    assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
+
+
+def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, monkeypatch):
+    say("query launch shapes")
+    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    n = keys.shape[0]
+    ref = None
+    for per_cu in ("1", "4", "32"):
+        monkeypatch.setenv("FLASH_QUERY_BLOCKS_PER_CU", per_cu)
+        out = gpu_query(fl, p, counts, ids, n, keys, 16, np.arange(n, dtype=np.int32))
+        if ref is None:
+            ref = out
+        assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
+
+
+# ------------------------------------------------------------------ whole path
+
+def _gpu_graph(fl, p, rp, ci, k):
+    import torch
+    n = rp.shape[0] - 1
+    counts, ids = fl.alloc_index(p)
+    ws = fl.alloc_workspace(fl.OP_KNN_GRAPH, p, n_rows=n, k=k)
+    oi = torch.empty(n * k, dtype=torch.int32, device="cuda")
+    oc = torch.empty(n * k, dtype=torch.int32, device="cuda")
+    rp_d = rp if hasattr(rp, "is_cuda") else dev(rp)
+    ci_d = ci if hasattr(ci, "is_cuda") else dev(ci)
+    fl.flash_knn_graph(p, rp_d, ci_d, k, counts, ids, oi, oc, ws)
+    torch.cuda.synchronize()
+    return counts, ids, oi.view(n, k), oc.view(n, k)
+
+
+def test_knn_graph_tiny_end_to_end(fl, orc):
+    from paper_1709_01190_amd import datagen
+    say("knn graph tiny")
+    rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    counts, ids, oi, oc = _gpu_graph(fl, p, rp, ci, 16)
+    okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(4, 16, 4, 32, seed=1), rp, ci, 16)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
+    assert np.array_equal(i32(oi), wi) and np.array_equal(i32(oc), wc)
+    r, nq = orc.recall_at_k(rp, ci, datagen.TINY.n_cols, np.arange(rp.shape[0] - 1), i32(oi))
+    say(f"tiny R@16 (Jaccard gold standard) = {r:.4f} over {nq} queries")
+
+
+def test_query_batch_from_csr(fl, orc):
+    import torch
+    from paper_1709_01190_amd import datagen
+    say("query batch csr")
+    rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    spec = datagen.scaled(datagen.TINY, 2000)
+    qrp, qci = (a.numpy() for a in datagen.make_rows(spec, 2))
+    op = orc.params(4, 16, 4, 32, seed=1)
+    okeys = orc.doph(op, rp, ci)
+    ocounts, oids = orc.build_tables(op, okeys)
+    wi, wc = orc.query(op, ocounts, oids, orc.doph(op, qrp, qci), 25)
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    counts, ids = fl.alloc_index(p)
+    n = rp.shape[0] - 1
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=n)
+    fl.flash_build_index(p, dev(rp), dev(ci), counts, ids, ws)
+    q = qrp.shape[0] - 1
+    oi = torch.empty(q * 25, dtype=torch.int32, device="cuda")
+    oc = torch.empty(q * 25, dtype=torch.int32, device="cuda")
+    qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=25)
+    fl.flash_query_batch(p, counts, ids, n, dev(qrp), dev(qci), 25, oi, oc, qws)
+    torch.cuda.synchronize()
+    assert np.array_equal(i32(oi).reshape(q, 25), wi) and np.array_equal(i32(oc).reshape(q, 25), wc)
+
+
+def test_url_shaped_graph(fl, orc):
+    # several hundred thousand rows, B = 160 (not a power of two), many
+    # saturated buckets (load above R)
+    from paper_1709_01190_amd import datagen
+    say("url-shaped 300k graph")
+    spec = datagen.scaled(datagen.URL, 300_000)
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
+    p = fl.flash_params.make(5, 32, 3, 64, seed=1)
+    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, 64)
+    okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(5, 32, 3, 64, seed=1), rp, ci, 64)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 32, 1 << 15, 64)
+    assert np.array_equal(i32(oi), wi) and np.array_equal(i32(oc), wc)

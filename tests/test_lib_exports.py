@@ -1,0 +1,98 @@
+"""The C-ABI library loads and exports every entry point include/flash.h declares
+(CPU only: no kernel is launched; only host-side argument checks run)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "flash.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"FLASH_API\s+[\w\s\*]*?\b(flash_\w+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def fl():
+    from paper_1709_01190_amd import flash
+    return flash
+
+
+def test_header_declares_the_four_hot_path_calls():
+    names = declared_functions()
+    for n in ("flash_hash", "flash_build_index", "flash_query_batch", "flash_knn_graph"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol(fl):
+    L = fl.lib()
+    missing = [n for n in declared_functions() if not hasattr(L, n)]
+    assert not missing, missing
+
+
+def test_library_exports_nothing_undeclared(fl):
+    import subprocess
+    out = subprocess.run(["nm", "-D", "--defined-only", fl.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = sorted({l.split()[-1] for l in out.splitlines() if " T " in l and "flash_" in l})
+    assert exported == declared_functions()
+
+
+def test_param_checks_run_on_the_host(fl):
+    P = fl.flash_params.make
+    fl.flash_check_params(P(4, 64, 4, 128))
+    fl.flash_check_params(P(5, 32, 3, 64))
+    for bad, code in [(P(0, 4, 4, 8), fl.FLASH_EINVAL), (P(4, 4, 8, 8), fl.FLASH_EINVAL),
+                      (P(4, 300, 1, 8), fl.FLASH_ENOTIMPL), (P(4, 64, 4, 2048), fl.FLASH_ENOTIMPL),
+                      (P(4, 64, 4, 256), fl.FLASH_ENOTIMPL)]:
+        with pytest.raises(fl.FlashError) as e:
+            fl.flash_check_params(bad)
+        assert e.value.code == code
+    p = P(4, 16, 4, 32)
+    bad = P(4, 16, 4, 32)
+    bad.reserved = 1
+    with pytest.raises(fl.FlashError):
+        fl.flash_check_params(bad)
+
+
+def test_index_and_workspace_sizes(fl):
+    p = fl.flash_params.make(4, 64, 4, 128)
+    ce, ie = fl.flash_index_elems(p)
+    assert ce == 64 * 65536 and ie == 64 * 65536 * 128
+    n = 350_000
+    ins = fl.flash_workspace_bytes(fl.OP_INSERT, p, n_rows=n)
+    assert ins >= 8 * n * 64 + 8 * 64 * 65536
+    g = fl.flash_workspace_bytes(fl.OP_KNN_GRAPH, p, n_rows=n, k=128)
+    assert g >= ins + 4 * n * 64
+    assert fl.flash_workspace_bytes(fl.OP_HASH, p, n_rows=n) == 0
+    with pytest.raises(fl.FlashError):
+        fl.flash_workspace_bytes(99, p)
+
+
+def test_device_calls_reject_bad_arguments_before_launch(fl):
+    # argument errors return before anything touches the GPU
+    L = fl.lib()
+    p = fl.flash_params.make(4, 16, 4, 32)
+    rc = L.flash_hash(ctypes.byref(p), 10, 100, None, None, None, None, None)
+    assert rc == fl.FLASH_EINVAL
+    rc = L.flash_insert_keys(ctypes.byref(p), 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                             ctypes.c_void_p(16), None, 0, None)
+    assert rc == fl.FLASH_ENOSPC
+    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), 10, 10,
+                            ctypes.c_void_p(16), None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                            ctypes.c_void_p(16), 1 << 20, None)
+    assert rc == fl.FLASH_EINVAL
+    assert b"k must be" in L.flash_last_error()
+
+
+def test_binding_refuses_cpu_tensors(fl):
+    import torch
+    p = fl.flash_params.make(4, 16, 4, 32)
+    rp = torch.zeros(3, dtype=torch.int64)
+    ci = torch.zeros(0, dtype=torch.int32)
+    keys = torch.zeros(2 * 16, dtype=torch.int32)
+    with pytest.raises(ValueError):
+        fl.flash_hash(p, rp, ci, keys)
