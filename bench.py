@@ -119,6 +119,11 @@ def main():
     occ = torch.clamp(cnt[torch.arange(L, device="cuda")[None, :], kq.clamp(0, M - 1)], max=R)
     occ = torch.where(kq >= 0, occ, torch.zeros_like(occ)) if kq.min() < 0 else occ
     occ_sum = int(occ.sum().item())
+    per_q = occ.sum(dim=1).float()
+    qs = torch.quantile(per_q[:min(n, 1 << 20)], torch.tensor([0.5, 0.9, 0.99, 1.0], device="cuda"))
+    log("occupied ids per query: mean %.1f p50 %.0f p90 %.0f p99 %.0f max %.0f; >1024: %.3f >2048: %.3f"
+        % (per_q.mean().item(), *qs.tolist(), (per_q > 1024).float().mean().item(),
+           (per_q > 2048).float().mean().item()))
     bytes_hash = 4 * nnz + 8 * (n + 1) + 4 * n * L
     n_ins = n * L
     nb = L * M

@@ -2,20 +2,26 @@
 // query hits, count how many of them hold each id, and return the k ids with
 // the highest counts (ties: smaller id first).
 //
-// One wavefront per query:
+// One wavefront per query, almost everything in registers:
 //   1. lane t reads key t and counts[t][key]; a wave scan gives each table's
 //      offset in the flattened candidate list (total = sum of occupancies);
-//   2. lanes walk the flattened list (a per-lane table cursor that only moves
-//      forward), load ids from HBM four at a time and add them to an LDS
-//      open-addressing table whose slot packs (id << cbits | count); the
-//      slots touched are recorded so that later passes and the final clear
-//      cost O(distinct candidates), not O(table size);
-//   3. a histogram of counts gives the threshold count c*; ids with count c*
-//      are cut by a radix select on the id (8 bits per pass);
-//   4. the k survivors are sorted by (count desc, id asc) with an LDS bitonic
-//      sort and written out.
-// Queries whose occupancy exceeds half the table go to an overflow list that
-// a second launch with a larger table handles.
+//   2. the wave walks the flattened list 256 candidates at a time; which
+//      table a lane's candidate belongs to is found by a wave-uniform loop
+//      over the tables in the window (readlane, no LDS), so four HBM loads
+//      per lane are in flight at once;
+//   3. each id goes into an LDS open-addressing table whose slot packs
+//      (id << cbits | count): one CAS claims an empty slot, a matching id
+//      adds 1.  Newly claimed slots are appended to a list with ballot/mbcnt
+//      offsets (no atomics), so every later pass costs O(distinct ids);
+//   4. a histogram of counts, kept one count value per lane and filled by a
+//      match loop (one ballot per distinct value), gives the threshold count
+//      c*; if too many ids tie at c*, an id threshold is found by counting
+//      with ballots (guessed from the uniform spread of ids, then bisected)
+//      so that between k and k + slack entries survive;
+//   5. survivors are ranked by (count desc, id asc) with broadcast LDS reads
+//      (no barriers) and written to their rank; slots are cleared on the way.
+// Queries with more candidates than a launch's table takes are appended to a
+// list that the next launch (a larger table) processes.
 #include "launch.hpp"
 
 namespace flashk {
@@ -31,256 +37,325 @@ struct QueryArgs {
   int32_t* out_counts;
   const uint32_t* qlist;      // process qlist[0 .. *qlist_len) if not null
   const uint32_t* qlist_len;
-  uint32_t* ovf_list;         // spill queries with total > CAP/2 here if not null
+  uint32_t* ovf_list;         // queries with total > max_total go here (null: never)
   uint32_t* ovf_len;
   int64_t n_queries;
+  int64_t n_indexed;
   uint32_t M;
-  int L, R, k, self_mode, cbits, top_shift;
-  uint32_t ks;                // power of two >= k
+  int L, R, k, self_mode, cbits;
+  uint32_t max_total;         // candidates this launch's table accepts
+  uint32_t sb;                // survivor buffer entries
 };
 
-struct Smem {
-  uint64_t* outk;  // [ks]
-  uint32_t* tab;   // [CAP]
-  uint16_t* used;  // [CAP / 2]
-  uint32_t* keysh; // [L]
-  uint32_t* pref;  // [L + 1]
-  uint32_t* hist;  // [max(L + 1, 256)]
-  uint32_t* scal;  // [4]: nused, nout
-};
+__host__ __device__ inline uint32_t slack_for(uint32_t need) { return need / 4 > 32 ? need / 4 : 32; }
 
-__host__ __device__ inline size_t smem_bytes(int cap, int L, uint32_t ks) {
-  const int nh = (L + 1) > 256 ? (L + 1) : 256;
-  return (size_t)ks * 8 + (size_t)cap * 4 + (size_t)cap + (size_t)L * 4 + (size_t)(L + 1) * 4 +
-         (size_t)nh * 4 + 16;
+__host__ __device__ inline size_t smem_bytes(int cap, uint32_t max_total, uint32_t sb) {
+  return (size_t)sb * 8 + (size_t)cap * 4 + (((size_t)max_total * 2 + 15) & ~(size_t)15);
 }
 
-template <int CAP>
-__device__ __forceinline__ void count_insert(const Smem& s, uint32_t id, int cbits) {
-  constexpr int kLog = __builtin_ctz(CAP);
-  uint32_t slot = (id * 0x9E3779B1u) >> (32 - kLog);
-  const uint32_t mine = (id << cbits) | 1u;
-  while (true) {
-    uint32_t cur = s.tab[slot];
-    if (cur == kEmpty) {
-      cur = atomicCAS(&s.tab[slot], kEmpty, mine);
-      if (cur == kEmpty) {
-        s.used[atomicAdd(&s.scal[0], 1u)] = (uint16_t)slot;
-        return;
-      }
-    }
-    if ((cur >> cbits) == id) {
-      atomicAdd(&s.tab[slot], 1u);
-      return;
-    }
-    slot = (slot + 1) & (CAP - 1);
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
+
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+__device__ __forceinline__ uint32_t rl(uint32_t v, uint32_t l) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, (int)l);
+}
+
+// value of a per-table register array (table t held by lane t & 63, chunk t >> 6)
+template <int LCH>
+__device__ __forceinline__ uint32_t tab_reg(const uint32_t (&r)[LCH], uint32_t t) {
+  if (LCH == 1) return rl(r[0], t);
+  const uint32_t c = t >> 6, l = t & 63;
+  uint32_t v = rl(r[0], l);
+  if (LCH > 1 && c == 1) v = rl(r[LCH > 1 ? 1 : 0], l);
+  if (LCH > 2 && c == 2) v = rl(r[LCH > 2 ? 2 : 0], l);
+  if (LCH > 3 && c == 3) v = rl(r[LCH > 3 ? 3 : 0], l);
+  return v;
+}
+
+template <int LCH>
+__device__ __forceinline__ void tab_reg_add(uint32_t (&r)[LCH], uint32_t t, uint32_t add) {
+  const uint32_t c = t >> 6, l = t & 63;
+  if (lane_id() == l) {
+#pragma unroll
+    for (int i = 0; i < LCH; ++i)
+      if ((uint32_t)i == c) r[i] += add;
   }
 }
 
-template <int CAP>
+template <int CAP, int LCH>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
+  constexpr int U = 4;                 // candidates per lane per round
+  constexpr int kLog = __builtin_ctz(CAP);
   extern __shared__ __align__(16) unsigned char smem[];
-  Smem s;
-  {
-    unsigned char* p = smem;
-    s.outk = (uint64_t*)p;
-    p += (size_t)a.ks * 8;
-    s.tab = (uint32_t*)p;
-    p += (size_t)CAP * 4;
-    s.used = (uint16_t*)p;
-    p += (size_t)CAP;
-    s.keysh = (uint32_t*)p;
-    p += (size_t)a.L * 4;
-    s.pref = (uint32_t*)p;
-    p += (size_t)(a.L + 1) * 4;
-    s.hist = (uint32_t*)p;
-    p += (size_t)((a.L + 1) > 256 ? (a.L + 1) : 256) * 4;
-    s.scal = (uint32_t*)p;
-  }
-  const uint32_t lane = threadIdx.x;
-  const int L = a.L;
-  const uint32_t cmask = (1u << a.cbits) - 1u;
+  uint64_t* sbuf = (uint64_t*)smem;                          // [sb]
+  uint32_t* tab = (uint32_t*)(smem + (size_t)a.sb * 8);      // [CAP]
+  uint16_t* used = (uint16_t*)(tab + CAP);                   // [max_total]
+
+  const uint32_t lane = lane_id();
+  const uint32_t L = (uint32_t)a.L;
   const uint32_t R = (uint32_t)a.R;
-  for (uint32_t i = lane; i < (uint32_t)CAP; i += kWave) s.tab[i] = kEmpty;
+  const uint32_t cb = (uint32_t)a.cbits;
+  const uint32_t cmask = (1u << cb) - 1u;
+  const uint32_t k = (uint32_t)a.k;
+  for (uint32_t i = lane; i < (uint32_t)CAP; i += kWave) tab[i] = kEmpty;
+  __syncthreads();
 
   const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
   for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
     const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
 
-    // 1. occupancy of the L buckets and their offsets
-    uint32_t carry = 0;
-    for (int t0 = 0; t0 < L; t0 += kWave) {
-      const int t = t0 + (int)lane;
+    // 1. occupancy and flattened offsets of the L buckets
+    uint32_t pref[LCH], blo[LCH], bhi[LCH];  // exclusive offset, 64-bit slot base of the bucket
+    uint32_t total = 0;
+#pragma unroll
+    for (int c = 0; c < LCH; ++c) {
+      const uint32_t t = (uint32_t)c * 64 + lane;
       uint32_t nt = 0;
+      uint64_t base = 0;
       if (t < L) {
         const uint32_t key = a.qkeys[q * (uint64_t)L + t];
         if (key < a.M) {
-          const uint32_t c = a.counts[(uint64_t)t * a.M + key];
-          nt = c < R ? c : R;
+          const uint64_t bucket = (uint64_t)t * a.M + key;
+          const uint32_t cnt = a.counts[bucket];
+          nt = cnt < R ? cnt : R;
+          base = bucket * R;
         }
-        s.keysh[t] = key;
       }
       const uint32_t inc = wave_incl_scan(nt);
-      if (t < L) s.pref[t] = carry + inc - nt;
-      carry += __shfl(inc, kWave - 1, kWave);
+      pref[c] = total + inc - nt;
+      blo[c] = (uint32_t)base;
+      bhi[c] = (uint32_t)(base >> 32);
+      total += rl(inc, 63);
     }
-    const uint32_t total = carry;
-    if (lane == 0) {
-      s.pref[L] = total;
-      s.scal[0] = 0;
-      s.scal[1] = 0;
-    }
-    __syncthreads();
-    if (total > (uint32_t)CAP / 2) {
+    if (total > a.max_total) {
       if (lane == 0) a.ovf_list[atomicAdd(a.ovf_len, 1u)] = (uint32_t)q;
-      __syncthreads();
       continue;
     }
 
-    // 2. gather and count
+    // 2-3. gather and count
+    uint32_t nd = 0;  // distinct ids so far (wave-uniform)
     {
-      uint32_t tc = 0;
-      constexpr int U = 4;
+      uint32_t t0 = 0;  // first table that may still hold candidates at or after `base`
       for (uint32_t base = 0; base < total; base += kWave * U) {
-        int32_t v[U];
+        uint32_t my_start[U];
+        uint64_t my_base[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          my_start[u] = 0;
+          my_base[u] = 0;
+        }
+        // tables whose ranges meet [base, base + 256)
+        while (t0 + 1 < L && tab_reg<LCH>(pref, t0 + 1) <= base) ++t0;
+        const uint32_t wend = base + kWave * U;
+        for (uint32_t t = t0; t < L; ++t) {
+          const uint32_t st = tab_reg<LCH>(pref, t);
+          if (st >= wend) break;
+          const uint64_t bb = ((uint64_t)tab_reg<LCH>(bhi, t) << 32) | tab_reg<LCH>(blo, t);
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            const uint32_t e = base + lane + kWave * u;
+            if (e >= st) {
+              my_start[u] = st;
+              my_base[u] = bb;
+            }
+          }
+        }
+        uint32_t id[U];
+        bool pend[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const uint32_t e = base + lane + kWave * u;
-          v[u] = -1;
-          if (e < total) {
-            while (s.pref[tc + 1] <= e) ++tc;
-            const uint64_t bucket = (uint64_t)tc * a.M + s.keysh[tc];
-            v[u] = a.ids[bucket * R + (e - s.pref[tc])];
+          pend[u] = e < total;
+          id[u] = pend[u] ? (uint32_t)a.ids[my_base[u] + (e - my_start[u])] : 0u;
+        }
+        uint32_t slot[U];
+        bool fresh[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          pend[u] = pend[u] && (int64_t)id[u] != self;
+          slot[u] = (id[u] * 0x9E3779B1u) >> (32 - kLog);
+          fresh[u] = false;
+        }
+        while (pend[0] || pend[1] || pend[2] || pend[3]) {
+          uint32_t old[U];
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            old[u] = pend[u] ? atomicCAS(&tab[slot[u]], kEmpty, (id[u] << cb) | 1u) : 0u;
+#pragma unroll
+          for (int u = 0; u < U; ++u) {
+            if (!pend[u]) continue;
+            if (old[u] == kEmpty) {
+              fresh[u] = true;
+              pend[u] = false;
+            } else if ((old[u] >> cb) == id[u]) {
+              atomicAdd(&tab[slot[u]], 1u);
+              pend[u] = false;
+            } else {
+              slot[u] = (slot[u] + 1) & (CAP - 1);
+            }
           }
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          if (v[u] >= 0 && (int64_t)v[u] != self) count_insert<CAP>(s, (uint32_t)v[u], a.cbits);
+        for (int u = 0; u < U; ++u) {
+          const uint64_t m = __ballot(fresh[u]);
+          if (fresh[u]) used[nd + mbcnt(m)] = (uint16_t)slot[u];
+          nd += (uint32_t)__popcll(m);
+        }
       }
     }
-    for (int c = (int)lane; c <= L; c += kWave) s.hist[c] = 0;
     __syncthreads();
-    const uint32_t nd = s.scal[0];
 
-    // 3. threshold count c* and tie cut
-    for (uint32_t i = lane; i < nd; i += kWave) atomicAdd(&s.hist[s.tab[s.used[i]] & cmask], 1u);
-    __syncthreads();
-    uint32_t cstar = 0, thr_id = 0xFFFFFFFFu;
-    if (nd > (uint32_t)a.k) {
-      uint32_t above = 0;  // ids with count > c*
+    // 4. histogram of counts (lane l, chunk c holds count value 1 + l + 64 c)
+    uint32_t cstar = 0, thr = 0xFFFFFFFFu;
+    if (nd > k) {
+      uint32_t hist[LCH];
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) hist[c] = 0;
+      for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
+        const uint32_t i = i0 + lane;
+        const bool valid = i < nd;
+        const uint32_t cv = valid ? (tab[used[i]] & cmask) : 0u;
+        uint64_t todo = __ballot(valid);
+        while (todo) {
+          const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1;
+          const uint32_t v = rl(cv, lead);
+          const uint64_t same = __ballot(valid && cv == v);
+          tab_reg_add<LCH>(hist, v - 1, (uint32_t)__popcll(same));
+          todo &= ~same;
+        }
+      }
+      // c*: the largest count with at least k ids at or above it
+      uint32_t above = 0;
       bool found = false;
-      for (int c0 = L; c0 >= 1 && !found; c0 -= kWave) {
-        const int c = c0 - (int)lane;
-        const uint32_t h = c >= 1 ? s.hist[c] : 0;
-        const uint32_t inc = wave_incl_scan(h);
-        const uint64_t hit = __ballot(above + inc >= (uint32_t)a.k);
+#pragma unroll
+      for (int c = LCH - 1; c >= 0; --c) {
+        if (found) continue;
+        const uint32_t rev = __shfl(hist[c], 63 - (int)lane, kWave);  // count 64c + 64 - lane
+        const uint32_t inc = wave_incl_scan(rev);
+        const uint64_t hit = __ballot(above + inc >= k);
         if (hit) {
-          const int f = __ffsll((unsigned long long)hit) - 1;
-          cstar = (uint32_t)(c0 - f);
-          above += __shfl(inc - h, f, kWave);
+          const uint32_t f = (uint32_t)__ffsll((unsigned long long)hit) - 1;
+          cstar = 64u * (uint32_t)c + 64u - f;
+          above += rl(inc - rev, f);
           found = true;
         } else {
-          above += __shfl(inc, kWave - 1, kWave);
+          above += rl(inc, 63);
         }
       }
-      const uint32_t need = (uint32_t)a.k - above;
-      const uint32_t ties = s.hist[cstar];
-      __syncthreads();
-      if (ties > need) {
-        uint32_t prefix = 0, rem = need;  // rem-th smallest tied id (1-based)
-        for (int sh = a.top_shift; sh >= 0; sh -= 8) {
-          for (uint32_t i = lane; i < 256; i += kWave) s.hist[i] = 0;
-          __syncthreads();
-          for (uint32_t i = lane; i < nd; i += kWave) {
-            const uint32_t vv = s.tab[s.used[i]];
-            const uint32_t id = vv >> a.cbits;
-            if ((vv & cmask) == cstar && (((uint64_t)(id ^ prefix)) >> (sh + 8)) == 0)
-              atomicAdd(&s.hist[(id >> sh) & 255u], 1u);
+      const uint32_t need = k - above;
+      const uint32_t ties = tab_reg<LCH>(hist, cstar - 1);
+      const uint32_t slack = slack_for(need);
+      if (ties > need + slack) {
+        // id threshold with need <= #(ties with id < thr) <= need + slack
+        const uint64_t span = (uint64_t)a.n_indexed;
+        uint64_t lo = 0, hi = span;
+        uint64_t g = ((uint64_t)(need + slack / 2) * span) / ties + 1;
+        if (g >= hi) g = hi - 1;
+        if (g <= lo) g = lo + 1;
+        for (int it = 0; it < 64; ++it) {
+          uint32_t cnt = 0;
+          for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
+            const uint32_t i = i0 + lane;
+            bool hit = false;
+            if (i < nd) {
+              const uint32_t v = tab[used[i]];
+              hit = (v & cmask) == cstar && (uint64_t)(v >> cb) < g;
+            }
+            cnt += (uint32_t)__popcll(__ballot(hit));
           }
-          __syncthreads();
-          const uint32_t h0 = s.hist[4 * lane], h1 = s.hist[4 * lane + 1], h2 = s.hist[4 * lane + 2],
-                         h3 = s.hist[4 * lane + 3];
-          const uint32_t sum4 = h0 + h1 + h2 + h3;
-          const uint32_t inc = wave_incl_scan(sum4);
-          const uint64_t hit = __ballot(inc >= rem);
-          const int f = __ffsll((unsigned long long)hit) - 1;
-          uint32_t cum = __shfl(inc - sum4, f, kWave);
-          const uint32_t g0 = __shfl(h0, f, kWave), g1 = __shfl(h1, f, kWave),
-                         g2 = __shfl(h2, f, kWave);
-          uint32_t d = 4 * (uint32_t)f;
-          if (cum + g0 >= rem) {
-          } else if (cum + g0 + g1 >= rem) {
-            d += 1;
-            cum += g0;
-          } else if (cum + g0 + g1 + g2 >= rem) {
-            d += 2;
-            cum += g0 + g1;
+          if (cnt < need) {
+            lo = g;
+          } else if (cnt > need + slack) {
+            hi = g;
           } else {
-            d += 3;
-            cum += g0 + g1 + g2;
+            break;
           }
-          prefix |= d << sh;
-          rem -= cum;
-          __syncthreads();
+          g = (lo + hi) / 2;
+          if (g == lo) break;  // cannot happen for distinct ids; keeps the loop finite
         }
-        thr_id = prefix;
+        thr = (uint32_t)g;
       }
     }
 
-    // 4. survivors, sorted by (count desc, id asc)
-    for (uint32_t i = lane; i < nd; i += kWave) {
-      const uint32_t vv = s.tab[s.used[i]];
-      const uint32_t c = vv & cmask, id = vv >> a.cbits;
-      if (c > cstar || (c == cstar && id <= thr_id)) {
-        const uint32_t pos = atomicAdd(&s.scal[1], 1u);
-        if (pos < a.ks) s.outk[pos] = ((uint64_t)(uint32_t)(L - (int)c) << 32) | id;
+    // 5. survivors -> sbuf (slots cleared on the way), then rank and write
+    uint32_t m = 0;
+    for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
+      const uint32_t i = i0 + lane;
+      bool sel = false;
+      uint64_t key = 0;
+      if (i < nd) {
+        const uint32_t s = used[i];
+        const uint32_t v = tab[s];
+        tab[s] = kEmpty;
+        const uint32_t c = v & cmask, idv = v >> cb;
+        sel = c > cstar || (c == cstar && idv < thr);
+        key = ((uint64_t)(L - c) << 32) | idv;
+      }
+      const uint64_t mk = __ballot(sel);
+      const uint32_t pos = m + mbcnt(mk);
+      if (sel && pos < a.sb) sbuf[pos] = key;
+      m += (uint32_t)__popcll(mk);
+    }
+    if (m > a.sb) m = a.sb;
+    __syncthreads();
+    const uint64_t orow = q * (uint64_t)k;
+    for (uint32_t j0 = 0; j0 < m; j0 += kWave) {
+      const uint32_t j = j0 + lane;
+      const uint64_t mine = j < m ? sbuf[j] : ~0ull;
+      uint32_t rank = 0;
+      uint32_t i = 0;
+      for (; i + 4 <= m; i += 4) {
+        rank += (sbuf[i] < mine) + (sbuf[i + 1] < mine) + (sbuf[i + 2] < mine) + (sbuf[i + 3] < mine);
+      }
+      for (; i < m; ++i) rank += sbuf[i] < mine;
+      if (j < m && rank < k) {
+        a.out_ids[orow + rank] = (int32_t)(uint32_t)mine;
+        a.out_counts[orow + rank] = (int32_t)L - (int32_t)(mine >> 32);
       }
     }
-    __syncthreads();
-    const uint32_t m = s.scal[1] < a.ks ? s.scal[1] : a.ks;
-    const uint32_t P = pow2_ceil(m);
-    for (uint32_t i = m + lane; i < P; i += kWave) s.outk[i] = ~0ull;
-    __syncthreads();
-    block64_bitonic_sort(s.outk, P);
-    for (uint32_t j = lane; j < (uint32_t)a.k; j += kWave) {
-      const uint64_t o = q * (uint64_t)a.k + j;
-      if (j < m) {
-        const uint64_t v = s.outk[j];
-        a.out_ids[o] = (int32_t)(uint32_t)v;
-        a.out_counts[o] = L - (int32_t)(v >> 32);
-      } else {
-        a.out_ids[o] = -1;
-        a.out_counts[o] = 0;
-      }
+    for (uint32_t j = m + lane; j < k; j += kWave) {
+      a.out_ids[orow + j] = -1;
+      a.out_counts[orow + j] = 0;
     }
-    // 5. leave the table empty for the next query
-    for (uint32_t i = lane; i < nd; i += kWave) s.tab[s.used[i]] = kEmpty;
     __syncthreads();
   }
 }
 
-template <int CAP>
+template <int CAP, int LCH>
 hipError_t launch_cap(const QueryArgs& a, int grid, hipStream_t st) {
-  const size_t lds = smem_bytes(CAP, a.L, a.ks);
+  const size_t lds = smem_bytes(CAP, a.max_total, a.sb);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&count_topk_kernel<CAP>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL(count_topk_kernel<CAP>, dim3(grid), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((count_topk_kernel<CAP, LCH>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_any(int cap, const QueryArgs& a, int grid, hipStream_t st) {
+template <int LCH>
+hipError_t launch_lch(int cap, const QueryArgs& a, int grid, hipStream_t st) {
   switch (cap) {
-    case 512: return launch_cap<512>(a, grid, st);
-    case 1024: return launch_cap<1024>(a, grid, st);
-    case 2048: return launch_cap<2048>(a, grid, st);
-    case 4096: return launch_cap<4096>(a, grid, st);
-    case 8192: return launch_cap<8192>(a, grid, st);
-    case 16384: return launch_cap<16384>(a, grid, st);
+    case 1024: return launch_cap<1024, LCH>(a, grid, st);
+    case 2048: return launch_cap<2048, LCH>(a, grid, st);
+    case 4096: return launch_cap<4096, LCH>(a, grid, st);
+    case 8192: return launch_cap<8192, LCH>(a, grid, st);
+    case 16384: return launch_cap<16384, LCH>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_any(int cap, const QueryArgs& a, int grid, hipStream_t st) {
+  switch ((a.L + 63) / 64) {
+    case 1: return launch_lch<1>(cap, a, grid, st);
+    case 2: return launch_lch<2>(cap, a, grid, st);
+    case 3: return launch_lch<3>(cap, a, grid, st);
+    case 4: return launch_lch<4>(cap, a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -293,16 +368,21 @@ int env_int(const char* name, int dflt) {
 }  // namespace
 
 size_t query_ws_bytes(const Cfg&, int64_t n_queries) {
-  return align256(4 * (uint64_t)(n_queries > 0 ? n_queries : 1)) + align256(4);
+  const uint64_t q = (uint64_t)(n_queries > 0 ? n_queries : 1);
+  return 2 * align256(4 * q) + align256(16);
 }
 
 QueryWs query_ws_carve(const Cfg&, int64_t n_queries, void* ws) {
+  const uint64_t q = (uint64_t)(n_queries > 0 ? n_queries : 1);
   QueryWs w;
-  w.ovf_list = (uint32_t*)ws;
-  w.ovf_len = (uint32_t*)((char*)ws + align256(4 * (uint64_t)(n_queries > 0 ? n_queries : 1)));
+  w.ovf_list[0] = (uint32_t*)ws;
+  w.ovf_list[1] = (uint32_t*)((char*)ws + align256(4 * q));
+  w.ovf_len = (uint32_t*)((char*)ws + 2 * align256(4 * q));
   return w;
 }
 
+// Query stages: each launch takes the queries whose candidate total fits its
+// table at <= 3/4 load (the last takes every query) and hands the rest on.
 hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
                         int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                         const int32_t* self_ids, int self_mode, int32_t k, int32_t* out_ids,
@@ -316,41 +396,57 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   a.out_ids = out_ids;
   a.out_counts = out_counts;
   a.n_queries = n_queries;
+  a.n_indexed = n_indexed > 0 ? n_indexed : 1;
   a.M = c.M;
   a.L = c.L;
   a.R = c.R;
   a.k = k;
   a.self_mode = self_mode;
   a.cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
-  const uint64_t maxid = n_indexed > 1 ? (uint64_t)(n_indexed - 1) : 1;
-  const int idbits = 64 - __builtin_clzll(maxid);
-  a.top_shift = ((idbits + 7) / 8) * 8 - 8;
-  a.ks = 1;
-  while (a.ks < (uint32_t)k) a.ks <<= 1;
 
-  const uint32_t full = 2u * (uint32_t)c.L * (uint32_t)c.R;  // table size that never overflows
-  uint32_t big = 512;
-  while (big < full) big <<= 1;
-  int cap = env_int("FLASH_QUERY_CAP", 2048);
-  if ((uint32_t)cap > big) cap = (int)big;
-  const int cus = device_info().cus;
-  const int per_cu = env_int("FLASH_QUERY_BLOCKS_PER_CU", 16);
-  const int64_t want = (int64_t)cus * per_cu;
-  const int grid = (int)(n_queries < want ? n_queries : want);
-  hipError_t e;
-  if ((uint32_t)cap >= big) {
-    return launch_any(cap, a, grid, st);
+  const uint32_t full = (uint32_t)c.L * (uint32_t)c.R;  // most candidates a query can have
+  uint32_t last = 1024;
+  while (last < 2 * full) last <<= 1;                   // table that takes any query at load 1/2
+  int caps[3];
+  int n_stage = 0;
+  // first and second table sizes (tuning knobs), rounded to a supported power of two
+  auto supported = [](int v) {
+    int c = 1024;
+    while (c < 16384 && 2 * c <= v) c <<= 1;
+    return c;
+  };
+  const int c0 = supported(env_int("FLASH_QUERY_CAP", 2048));
+  const int c1 = supported(env_int("FLASH_QUERY_CAP2", 8192));
+  for (int cap : {c0, c1}) {
+    if ((uint32_t)cap >= last) break;
+    if (n_stage == 0 || cap > caps[n_stage - 1]) caps[n_stage++] = cap;
   }
-  a.ovf_list = w.ovf_list;
-  a.ovf_len = w.ovf_len;
-  if ((e = launch_fill_u32(w.ovf_len, 1, 0u, st)) != hipSuccess) return e;
-  if ((e = launch_any(cap, a, grid, st)) != hipSuccess) return e;
-  QueryArgs b = a;
-  b.qlist = w.ovf_list;
-  b.qlist_len = w.ovf_len;
-  b.ovf_list = nullptr;
-  b.ovf_len = nullptr;
-  return launch_any((int)big, b, cus * 2, st);
+  caps[n_stage++] = (int)last;
+
+  const int cus = device_info().cus;
+  const int per_cu = env_int("FLASH_QUERY_BLOCKS_PER_CU", 32);
+  hipError_t e;
+  if (n_stage > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
+  for (int s = 0; s < n_stage; ++s) {
+    QueryArgs b = a;
+    const bool final_stage = s == n_stage - 1;
+    b.max_total = final_stage ? full : (uint32_t)caps[s] * 3 / 4;
+    const uint32_t need_sb = (uint32_t)k + slack_for((uint32_t)k);
+    b.sb = need_sb < b.max_total ? need_sb : (b.max_total > (uint32_t)k ? b.max_total : (uint32_t)k);
+    if (s > 0) {
+      b.qlist = w.ovf_list[(s - 1) & 1];
+      b.qlist_len = w.ovf_len + ((s - 1) & 1);
+    }
+    if (!final_stage) {
+      b.ovf_list = w.ovf_list[s & 1];
+      b.ovf_len = w.ovf_len + (s & 1);
+    }
+    int64_t want = (int64_t)cus * per_cu;
+    if (s > 0) want = (int64_t)cus * 8;
+    const int grid = (int)(n_queries < want ? n_queries : want);
+    if ((e = launch_any(caps[s], b, grid, st)) != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace flashk

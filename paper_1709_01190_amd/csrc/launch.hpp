@@ -42,8 +42,8 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
 
 // ---- query (count_topk.hip)
 struct QueryWs {
-  uint32_t* ovf_list;   // [n_queries]    queries whose candidates overflow the main table
-  uint32_t* ovf_len;    // [1]
+  uint32_t* ovf_list[2];  // [n_queries] each: queries handed on to the next (larger) table
+  uint32_t* ovf_len;      // [4]
 };
 size_t query_ws_bytes(const Cfg& c, int64_t n_queries);
 QueryWs query_ws_carve(const Cfg& c, int64_t n_queries, void* ws);

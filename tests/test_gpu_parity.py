@@ -285,7 +285,7 @@ def test_query_overflow_table(fl, orc, monkeypatch):
     qk = keys[:700].copy()
     qk[100:400, 4:] = EMPTY     # small queries stay in the first pass
     wi, wc = orc.query(op, ocounts, oids, qk, 300, self_ids=np.arange(700, dtype=np.int32))
-    for cap in ("512", "2048", "16384"):
+    for cap in ("1024", "2048", "16384"):
         monkeypatch.setenv("FLASH_QUERY_CAP", cap)
         oi, oc = gpu_query(fl, p, counts, ids, n, qk, 300, np.arange(700, dtype=np.int32))
         assert np.array_equal(oi, wi) and np.array_equal(oc, wc), cap
