@@ -50,7 +50,13 @@ def main():
     ap.add_argument("--cpu-queries", type=int, default=20000,
                     help="queries the CPU oracle answers (the rest is extrapolated)")
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--copy-mib", type=int, default=0,
+                    help="instead of the benchmark, copy this many MiB device to device (a plain "
+                         "copy kernel of known size that calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_mib:
+        copy_calibration(args.copy_mib)
+        return
 
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
@@ -179,6 +185,22 @@ def main():
         "phases": phases,
     }
     print(json.dumps(out), flush=True)
+
+
+def copy_calibration(mib):
+    import torch
+    n = mib * (1 << 20) // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    dst.copy_(src)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": round(ms, 4),
+                      "GBps": round(8 * n / (ms * 1e6), 1)}), flush=True)
 
 
 def _kernel_source_sha():

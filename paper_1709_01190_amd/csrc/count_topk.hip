@@ -47,10 +47,11 @@ struct QueryArgs {
   uint32_t sb;                // survivor buffer entries
 };
 
-__host__ __device__ inline uint32_t slack_for(uint32_t need) { return need / 4 > 32 ? need / 4 : 32; }
+__host__ __device__ inline uint32_t slack_for(uint32_t need) { return need / 8 > 16 ? need / 8 : 16; }
 
-__host__ __device__ inline size_t smem_bytes(int cap, uint32_t max_total, uint32_t sb) {
-  return (size_t)sb * 8 + (size_t)cap * 4 + (((size_t)max_total * 2 + 15) & ~(size_t)15);
+__host__ __device__ inline size_t smem_bytes(int cap, int L, uint32_t sb) {
+  const size_t scratch = sb > 256 ? sb : 256;
+  return (size_t)cap * 4 + scratch * 4 + (size_t)L * 12 + (size_t)(L + 1) * 4 + 16;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
@@ -85,14 +86,130 @@ __device__ __forceinline__ void tab_reg_add(uint32_t (&r)[LCH], uint32_t t, uint
   }
 }
 
+__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
+  const int lane = threadIdx.x & (kWave - 1);
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, kWave);
+    if (lane >= d) v = v > o ? v : o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
+  return v;
+}
+
+// Sort m <= 64 * KPL keys held in scratch (ascending) across the wave, KPL
+// keys per lane (element i = lane * KPL + r), and write the first k as
+// (id, count); positions past m get (-1, 0).
+template <int KPL>
+__device__ __forceinline__ void sort_write(const uint32_t* scratch, uint32_t m, uint32_t k, uint32_t L,
+                                           uint32_t idshift, uint32_t idmask, int32_t* out_ids,
+                                           int32_t* out_counts) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t x[KPL];
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    const uint32_t i = lane * KPL + (uint32_t)r;
+    x[r] = i < m ? scratch[i] : 0xFFFFFFFFu;
+  }
+#pragma unroll
+  for (uint32_t kk = 2; kk <= 64u * KPL; kk <<= 1) {
+#pragma unroll
+    for (uint32_t j = kk >> 1; j > 0; j >>= 1) {
+      if (j < (uint32_t)KPL) {
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          if ((r & j) != 0) continue;
+          const uint32_t i = lane * KPL + (uint32_t)r;
+          const uint32_t p = x[r], q = x[r ^ j];
+          const bool up = (i & kk) == 0;
+          const uint32_t mn = p < q ? p : q, mx = p < q ? q : p;
+          x[r] = up ? mn : mx;
+          x[r ^ j] = up ? mx : mn;
+        }
+      } else {
+        const uint32_t lj = j / KPL;
+#pragma unroll
+        for (int r = 0; r < KPL; ++r) {
+          const uint32_t i = lane * KPL + (uint32_t)r;
+          const uint32_t o = (uint32_t)__shfl_xor((int)x[r], (int)lj, kWave);
+          const bool up = (i & kk) == 0, lower = (lane & lj) == 0;
+          const uint32_t mn = x[r] < o ? x[r] : o, mx = x[r] < o ? o : x[r];
+          x[r] = (lower == up) ? mn : mx;
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < KPL; ++r) {
+    const uint32_t i = lane * KPL + (uint32_t)r;
+    if (i < k) {
+      const bool real = i < m;
+      out_ids[i] = real ? (int32_t)(x[r] & idmask) : -1;
+      out_counts[i] = real ? (int32_t)L - (int32_t)(x[r] >> idshift) : 0;
+    }
+  }
+  for (uint32_t i = 64u * KPL + lane; i < k; i += kWave) {
+    out_ids[i] = -1;
+    out_counts[i] = 0;
+  }
+}
+
+// Same result for any m: each key's rank is the number of smaller keys.
+__device__ __forceinline__ void rank_write(const uint32_t* scratch, uint32_t m, uint32_t k, uint32_t L,
+                                           uint32_t idshift, uint32_t idmask, int32_t* out_ids,
+                                           int32_t* out_counts) {
+  const uint32_t lane = threadIdx.x & 63;
+  for (uint32_t j0 = 0; j0 < m; j0 += 4 * kWave) {
+    uint32_t key[4], rank[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t j = j0 + (uint32_t)r * kWave + lane;
+      key[r] = j < m ? scratch[j] : 0xFFFFFFFFu;
+      rank[r] = 0;
+    }
+    uint32_t i = 0;
+    for (; i + 4 <= m; i += 4) {
+      const uint4 o = *reinterpret_cast<const uint4*>(scratch + i);
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        rank[r] += (o.x < key[r]) + (o.y < key[r]) + (o.z < key[r]) + (o.w < key[r]);
+    }
+    for (; i < m; ++i) {
+      const uint32_t o = scratch[i];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rank[r] += o < key[r];
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const uint32_t j = j0 + (uint32_t)r * kWave + lane;
+      if (j < m && rank[r] < k) {
+        out_ids[rank[r]] = (int32_t)(key[r] & idmask);
+        out_counts[rank[r]] = (int32_t)L - (int32_t)(key[r] >> idshift);
+      }
+    }
+  }
+  for (uint32_t j = m + lane; j < k; j += kWave) {
+    out_ids[j] = -1;
+    out_counts[j] = 0;
+  }
+}
+
 template <int CAP, int LCH>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
-  constexpr int U = 4;                 // candidates per lane per round
+  constexpr int U = 4;                 // candidates per lane per window
+  constexpr int W = kWave * U;         // window of the flattened candidate list
   constexpr int kLog = __builtin_ctz(CAP);
   extern __shared__ __align__(16) unsigned char smem[];
-  uint64_t* sbuf = (uint64_t*)smem;                          // [sb]
-  uint32_t* tab = (uint32_t*)(smem + (size_t)a.sb * 8);      // [CAP]
-  uint16_t* used = (uint16_t*)(tab + CAP);                   // [max_total]
+  uint32_t* tab = (uint32_t*)smem;                         // [CAP] packed (id << cbits | count)
+  uint32_t* scratch = tab + CAP;                           // [max(W, sb)] window marks, then survivors
+  uint32_t* tpref = scratch + (a.sb > (uint32_t)W ? a.sb : (uint32_t)W);  // [L] table offsets
+  uint32_t* tbase = tpref + a.L;                           // [2 L] 64-bit slot bases (lo, hi)
+  uint32_t* hist = tbase + 2 * a.L;                        // [L + 1]
 
   const uint32_t lane = lane_id();
   const uint32_t L = (uint32_t)a.L;
@@ -100,7 +217,10 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   const uint32_t cb = (uint32_t)a.cbits;
   const uint32_t cmask = (1u << cb) - 1u;
   const uint32_t k = (uint32_t)a.k;
-  for (uint32_t i = lane; i < (uint32_t)CAP; i += kWave) tab[i] = kEmpty;
+  const uint32_t idshift = 32u - cb;   // survivor key = (L - count) << idshift | id
+  uint4* tab4 = reinterpret_cast<uint4*>(tab);
+  for (uint32_t i = lane; i < (uint32_t)CAP / 4; i += kWave) tab4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (uint32_t i = lane; i < (uint32_t)W; i += kWave) scratch[i] = kEmpty;
   __syncthreads();
 
   const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
@@ -109,7 +229,7 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
 
     // 1. occupancy and flattened offsets of the L buckets
-    uint32_t pref[LCH], blo[LCH], bhi[LCH];  // exclusive offset, 64-bit slot base of the bucket
+    uint32_t pref[LCH], nts[LCH];
     uint32_t total = 0;
 #pragma unroll
     for (int c = 0; c < LCH; ++c) {
@@ -127,130 +247,134 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
       }
       const uint32_t inc = wave_incl_scan(nt);
       pref[c] = total + inc - nt;
-      blo[c] = (uint32_t)base;
-      bhi[c] = (uint32_t)(base >> 32);
+      nts[c] = nt;
+      if (t < L) {
+        tpref[t] = pref[c];
+        tbase[2 * t] = (uint32_t)base;
+        tbase[2 * t + 1] = (uint32_t)(base >> 32);
+      }
       total += rl(inc, 63);
     }
     if (total > a.max_total) {
       if (lane == 0) a.ovf_list[atomicAdd(a.ovf_len, 1u)] = (uint32_t)q;
       continue;
     }
-
-    // 2-3. gather and count
-    uint32_t nd = 0;  // distinct ids so far (wave-uniform)
-    {
-      uint32_t t0 = 0;  // first table that may still hold candidates at or after `base`
-      for (uint32_t base = 0; base < total; base += kWave * U) {
-        uint32_t my_start[U];
-        uint64_t my_base[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          my_start[u] = 0;
-          my_base[u] = 0;
-        }
-        // tables whose ranges meet [base, base + 256)
-        while (t0 + 1 < L && tab_reg<LCH>(pref, t0 + 1) <= base) ++t0;
-        const uint32_t wend = base + kWave * U;
-        for (uint32_t t = t0; t < L; ++t) {
-          const uint32_t st = tab_reg<LCH>(pref, t);
-          if (st >= wend) break;
-          const uint64_t bb = ((uint64_t)tab_reg<LCH>(bhi, t) << 32) | tab_reg<LCH>(blo, t);
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            const uint32_t e = base + lane + kWave * u;
-            if (e >= st) {
-              my_start[u] = st;
-              my_base[u] = bb;
-            }
-          }
-        }
-        uint32_t id[U];
-        bool pend[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint32_t e = base + lane + kWave * u;
-          pend[u] = e < total;
-          id[u] = pend[u] ? (uint32_t)a.ids[my_base[u] + (e - my_start[u])] : 0u;
-        }
-        uint32_t slot[U];
-        bool fresh[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          pend[u] = pend[u] && (int64_t)id[u] != self;
-          slot[u] = (id[u] * 0x9E3779B1u) >> (32 - kLog);
-          fresh[u] = false;
-        }
-        while (pend[0] || pend[1] || pend[2] || pend[3]) {
-          uint32_t old[U];
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-            old[u] = pend[u] ? atomicCAS(&tab[slot[u]], kEmpty, (id[u] << cb) | 1u) : 0u;
-#pragma unroll
-          for (int u = 0; u < U; ++u) {
-            if (!pend[u]) continue;
-            if (old[u] == kEmpty) {
-              fresh[u] = true;
-              pend[u] = false;
-            } else if ((old[u] >> cb) == id[u]) {
-              atomicAdd(&tab[slot[u]], 1u);
-              pend[u] = false;
-            } else {
-              slot[u] = (slot[u] + 1) & (CAP - 1);
-            }
-          }
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const uint64_t m = __ballot(fresh[u]);
-          if (fresh[u]) used[nd + mbcnt(m)] = (uint16_t)slot[u];
-          nd += (uint32_t)__popcll(m);
-        }
-      }
-    }
+    for (uint32_t c = lane; c <= L; c += kWave) hist[c] = 0;
     __syncthreads();
 
-    // 4. histogram of counts (lane l, chunk c holds count value 1 + l + 64 c)
-    uint32_t cstar = 0, thr = 0xFFFFFFFFu;
-    if (nd > k) {
-      uint32_t hist[LCH];
+    // 2-3. gather and count, one window of W candidates at a time
+    for (uint32_t base = 0; base < total; base += W) {
+      // mark where each non-empty table starts inside the window; the table
+      // holding the window's first candidate is marked at position 0
+      uint32_t tf = 0;
 #pragma unroll
-      for (int c = 0; c < LCH; ++c) hist[c] = 0;
-      for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
-        const uint32_t i = i0 + lane;
-        const bool valid = i < nd;
-        const uint32_t cv = valid ? (tab[used[i]] & cmask) : 0u;
-        uint64_t todo = __ballot(valid);
-        while (todo) {
-          const uint32_t lead = (uint32_t)__ffsll((unsigned long long)todo) - 1;
-          const uint32_t v = rl(cv, lead);
-          const uint64_t same = __ballot(valid && cv == v);
-          tab_reg_add<LCH>(hist, v - 1, (uint32_t)__popcll(same));
-          todo &= ~same;
+      for (int c = 0; c < LCH; ++c) {
+        const uint32_t t = (uint32_t)c * 64 + lane;
+        const bool ne = nts[c] > 0;
+        if (ne && pref[c] > base && pref[c] < base + W) scratch[pref[c] - base] = t;
+        const uint64_t bal = __ballot(ne && pref[c] <= base);
+        if (bal) tf = (uint32_t)c * 64 + 63 - (uint32_t)__clzll((long long)bal);
+      }
+      if (lane == 0) scratch[0] = tf;
+      __syncthreads();
+      uint32_t carry = 0;
+      uint32_t id[U];
+      bool pend[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t mk = scratch[u * kWave + lane];
+        scratch[u * kWave + lane] = kEmpty;
+        uint32_t t = wave_incl_max(mk == kEmpty ? 0u : mk + 1);  // 0 = no mark yet
+        t = t > carry ? t : carry;
+        carry = rl(t, 63);
+        const uint32_t e = base + (uint32_t)u * kWave + lane;
+        pend[u] = e < total;
+        id[u] = 0;
+        if (pend[u]) {
+          const uint32_t tt = t - 1;
+          const uint64_t sb = ((uint64_t)tbase[2 * tt + 1] << 32) | tbase[2 * tt];
+          id[u] = (uint32_t)a.ids[sb + (e - tpref[tt])];
         }
       }
+      uint32_t slot[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        pend[u] = pend[u] && (int64_t)id[u] != self;
+        slot[u] = (id[u] * 0x9E3779B1u) >> (32 - kLog);
+      }
+      while (pend[0] || pend[1] || pend[2] || pend[3]) {
+        uint32_t old[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          old[u] = pend[u] ? atomicCAS(&tab[slot[u]], kEmpty, (id[u] << cb) | 1u) : 0u;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          if (!pend[u]) continue;
+          if (old[u] == kEmpty) {
+            pend[u] = false;
+          } else if ((old[u] >> cb) == id[u]) {
+            atomicAdd(&tab[slot[u]], 1u);
+            pend[u] = false;
+          } else {
+            slot[u] = (slot[u] + 1) & (CAP - 1);
+          }
+        }
+      }
+      __syncthreads();
+    }
+
+    // 4. compact the distinct entries to tab[0, nd) in place (each chunk is
+    // read and cleared before compacted entries are written into it), then
+    // histogram the counts: count 1 in registers, larger counts in LDS
+    uint32_t nd = 0;
+    for (uint32_t i0 = 0; i0 < (uint32_t)CAP / 4; i0 += kWave) {
+      const uint4 v4 = tab4[i0 + lane];
+      tab4[i0 + lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+      const uint32_t n4 = (v4.x != kEmpty) + (v4.y != kEmpty) + (v4.z != kEmpty) + (v4.w != kEmpty);
+      const uint32_t inc = wave_incl_scan(n4);
+      uint32_t pos = nd + inc - n4;
+      if (v4.x != kEmpty) tab[pos++] = v4.x;
+      if (v4.y != kEmpty) tab[pos++] = v4.y;
+      if (v4.z != kEmpty) tab[pos++] = v4.z;
+      if (v4.w != kEmpty) tab[pos++] = v4.w;
+      nd += rl(inc, 63);
+    }
+    __syncthreads();
+    uint32_t ones = 0;
+    for (uint32_t i = lane; i < nd; i += kWave) {
+      const uint32_t c = tab[i] & cmask;
+      if (c == 1) ++ones;
+      else atomicAdd(&hist[c], 1u);
+    }
+    ones = wave_sum(ones);
+    if (lane == 0) hist[1] = ones;
+    __syncthreads();
+
+    uint32_t cstar = 0, thr = 0xFFFFFFFFu;
+    if (nd > k) {
       // c*: the largest count with at least k ids at or above it
       uint32_t above = 0;
       bool found = false;
-#pragma unroll
-      for (int c = LCH - 1; c >= 0; --c) {
-        if (found) continue;
-        const uint32_t rev = __shfl(hist[c], 63 - (int)lane, kWave);  // count 64c + 64 - lane
-        const uint32_t inc = wave_incl_scan(rev);
+      for (int c0 = (int)L; c0 >= 1 && !found; c0 -= kWave) {
+        const int c = c0 - (int)lane;
+        const uint32_t h = c >= 1 ? hist[c] : 0u;
+        const uint32_t inc = wave_incl_scan(h);
         const uint64_t hit = __ballot(above + inc >= k);
         if (hit) {
           const uint32_t f = (uint32_t)__ffsll((unsigned long long)hit) - 1;
-          cstar = 64u * (uint32_t)c + 64u - f;
-          above += rl(inc - rev, f);
+          cstar = (uint32_t)(c0 - (int)f);
+          above += rl(inc - h, f);
           found = true;
         } else {
           above += rl(inc, 63);
         }
       }
       const uint32_t need = k - above;
-      const uint32_t ties = tab_reg<LCH>(hist, cstar - 1);
+      const uint32_t ties = hist[cstar];
       const uint32_t slack = slack_for(need);
       if (ties > need + slack) {
-        // id threshold with need <= #(ties with id < thr) <= need + slack
+        // id threshold with need <= #(ties with id < thr) <= need + slack,
+        // guessed from the uniform spread of ids, then bisected
         const uint64_t span = (uint64_t)a.n_indexed;
         uint64_t lo = 0, hi = span;
         uint64_t g = ((uint64_t)(need + slack / 2) * span) / ties + 1;
@@ -258,15 +382,11 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
         if (g <= lo) g = lo + 1;
         for (int it = 0; it < 64; ++it) {
           uint32_t cnt = 0;
-          for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
-            const uint32_t i = i0 + lane;
-            bool hit = false;
-            if (i < nd) {
-              const uint32_t v = tab[used[i]];
-              hit = (v & cmask) == cstar && (uint64_t)(v >> cb) < g;
-            }
-            cnt += (uint32_t)__popcll(__ballot(hit));
+          for (uint32_t i = lane; i < nd; i += kWave) {
+            const uint32_t v = tab[i];
+            cnt += (v & cmask) == cstar && (uint64_t)(v >> cb) < g;
           }
+          cnt = wave_sum(cnt);
           if (cnt < need) {
             lo = g;
           } else if (cnt > need + slack) {
@@ -281,53 +401,46 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
       }
     }
 
-    // 5. survivors -> sbuf (slots cleared on the way), then rank and write
+    // 5. survivors -> scratch (tab[0, nd) is cleared on the way), sort, write
     uint32_t m = 0;
     for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
       const uint32_t i = i0 + lane;
       bool sel = false;
-      uint64_t key = 0;
+      uint32_t key = 0;
       if (i < nd) {
-        const uint32_t s = used[i];
-        const uint32_t v = tab[s];
-        tab[s] = kEmpty;
+        const uint32_t v = tab[i];
+        tab[i] = kEmpty;
         const uint32_t c = v & cmask, idv = v >> cb;
         sel = c > cstar || (c == cstar && idv < thr);
-        key = ((uint64_t)(L - c) << 32) | idv;
+        key = ((L - c) << idshift) | idv;
       }
       const uint64_t mk = __ballot(sel);
       const uint32_t pos = m + mbcnt(mk);
-      if (sel && pos < a.sb) sbuf[pos] = key;
+      if (sel && pos < a.sb) scratch[pos] = key;
       m += (uint32_t)__popcll(mk);
     }
     if (m > a.sb) m = a.sb;
     __syncthreads();
     const uint64_t orow = q * (uint64_t)k;
-    for (uint32_t j0 = 0; j0 < m; j0 += kWave) {
-      const uint32_t j = j0 + lane;
-      const uint64_t mine = j < m ? sbuf[j] : ~0ull;
-      uint32_t rank = 0;
-      uint32_t i = 0;
-      for (; i + 4 <= m; i += 4) {
-        rank += (sbuf[i] < mine) + (sbuf[i + 1] < mine) + (sbuf[i + 2] < mine) + (sbuf[i + 3] < mine);
-      }
-      for (; i < m; ++i) rank += sbuf[i] < mine;
-      if (j < m && rank < k) {
-        a.out_ids[orow + rank] = (int32_t)(uint32_t)mine;
-        a.out_counts[orow + rank] = (int32_t)L - (int32_t)(mine >> 32);
-      }
-    }
-    for (uint32_t j = m + lane; j < k; j += kWave) {
-      a.out_ids[orow + j] = -1;
-      a.out_counts[orow + j] = 0;
+    const uint32_t idmask = (idshift >= 32) ? 0xFFFFFFFFu : ((1u << idshift) - 1u);
+    if (m <= 64) {
+      sort_write<1>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+    } else if (m <= 128) {
+      sort_write<2>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+    } else if (m <= 256) {
+      sort_write<4>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+    } else {
+      rank_write(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
     }
     __syncthreads();
+    // leave the window marks empty for the next query
+    for (uint32_t i = lane; i < (uint32_t)W; i += kWave) scratch[i] = kEmpty;
   }
 }
 
 template <int CAP, int LCH>
 hipError_t launch_cap(const QueryArgs& a, int grid, hipStream_t st) {
-  const size_t lds = smem_bytes(CAP, a.max_total, a.sb);
+  const size_t lds = smem_bytes(CAP, a.L, a.sb);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH>),
@@ -416,7 +529,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     return c;
   };
   const int c0 = supported(env_int("FLASH_QUERY_CAP", 2048));
-  const int c1 = supported(env_int("FLASH_QUERY_CAP2", 8192));
+  const int c1 = supported(env_int("FLASH_QUERY_CAP2", 4096));
   for (int cap : {c0, c1}) {
     if ((uint32_t)cap >= last) break;
     if (n_stage == 0 || cap > caps[n_stage - 1]) caps[n_stage++] = cap;

@@ -5,7 +5,7 @@
 #include <mutex>
 #include <string>
 
-#include "../../include/flash.h"
+#include "flash.h"
 #include "launch.hpp"
 
 namespace flashk {

@@ -28,11 +28,13 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
 
 // ---- insert (reservoir_insert.hip)
 struct InsertWs {
-  uint32_t* rank;       // [n_rows * L]   arrival rank inside its bucket
-  int32_t* staged;      // [n_rows * L]   ids grouped by bucket
+  uint32_t* keys_t;     // [L][np]        table-major keys (rows padded to 64)
+  int32_t* staged;      // [n_rows * L]   row ids grouped by bucket
+  uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)
+  uint32_t* partoff;    // [L * M * S]    exclusive prefix of part
   uint32_t* seg;        // [L * M]        first staged slot of each bucket
-  uint32_t* tile_sums;  // [tiles + 1]    scan carries
   uint32_t* worklist;   // [L * M]        buckets for the wave-level select
+  uint32_t* tile_sums;  // [tiles + 1]    scan carries
   uint32_t* wl_len;     // [1]
 };
 size_t insert_ws_bytes(const Cfg& c, int64_t n_rows);

@@ -1,17 +1,24 @@
 // Adding phase (paper Alg. 2) with fixed-size reservoirs (Sec. 2.4, Alg. 1),
 // read as bottom-R priority sampling so that the tables do not depend on the
-// order in which GPU atomics land.
+// order in which arrivals are processed.
 //
-//   count   : counts[t][m] += 1 for every (row, t); the returned old value is
-//             the arrival's rank inside its bucket (Alg. 2's ReservoirCounter)
-//   scan    : seg = exclusive prefix sum of counts over all L*M buckets
-//   scatter : staged[seg[t][m] + rank] = row
-//   select  : per bucket, the min(count, R) arrivals with the smallest
-//             priority, in ascending priority, into ids[t][m][0..)
-//             - buckets of <= 8 arrivals: one thread, ranks in registers
-//             - larger buckets: one wave; all arrivals sorted in LDS when few,
-//               else a priority threshold keeps ~2R candidates (bisected until
-//               between R and the LDS capacity), which are then sorted.
+// A counting sort of the (table, key) arrivals, privatised in LDS so that no
+// global atomics are needed:
+//   transpose : keys[N][L] -> keysT[L][Np] (table-major, rows padded to 64)
+//   count     : block (t, chunk, slice) histograms the keys of table t that
+//               fall in its chunk of CH buckets, over its slice of rows, in
+//               LDS; part[(t*M + m) * S + slice] = that count
+//   scan      : partoff = exclusive prefix sum of part (bucket-major, slice
+//               minor), so every (bucket, slice) owns a run of `staged`
+//   totals    : counts[t][m] = sum over slices (Alg. 2's ReservoirCounter),
+//               seg[t][m] = first staged slot of the bucket
+//   scatter   : the same blocks place each arrival's row id at an LDS cursor
+//   select    : per bucket, the min(count, R) arrivals with the smallest
+//               priority, in ascending priority, into ids[t][m][0..)
+//               - buckets of <= 8 arrivals: one thread, ranks in registers
+//               - larger buckets: one wave; all arrivals sorted in LDS when few,
+//                 else a priority threshold keeps ~2R candidates (bisected until
+//                 between R and the LDS capacity), which are then sorted.
 // Every step is a deterministic function of the keys, so the result is
 // bit-identical for any scheduling.
 #include "launch.hpp"
@@ -32,13 +39,97 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
-__global__ void insert_count_kernel(const uint32_t* __restrict__ keys, uint32_t n_elems, uint32_t L,
-                                    uint32_t M, uint32_t* counts, uint32_t* __restrict__ rank) {
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_elems; e += gridDim.x * blockDim.x) {
-    const uint32_t k = keys[e];
-    uint32_t r = kEmpty;
-    if (k < M) r = atomicAdd(&counts[(uint64_t)(e % L) * M + k], 1u);
-    rank[e] = r;
+constexpr uint32_t kChunk = 16384;  // buckets per LDS histogram (64 KiB)
+constexpr int kPartThreads = 512;
+
+__global__ __launch_bounds__(256) void keys_transpose_kernel(const uint32_t* __restrict__ keys, uint32_t n,
+                                                             uint32_t L, uint32_t np,
+                                                             uint32_t* __restrict__ keys_t) {
+  __shared__ uint32_t tile[64][65];
+  const uint32_t row0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
+  for (uint32_t i = threadIdx.x; i < 64 * 64; i += 256) {
+    const uint32_t r = i >> 6, c = i & 63, row = row0 + r, t = t0 + c;
+    tile[r][c] = (row < n && t < L) ? keys[(uint64_t)row * L + t] : kEmpty;
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < 64 * 64; i += 256) {
+    const uint32_t c = i >> 6, r = i & 63, row = row0 + r, t = t0 + c;
+    if (t < L && row < np) keys_t[(uint64_t)t * np + row] = tile[r][c];
+  }
+}
+
+struct PartArgs {
+  const uint32_t* keys_t;  // [L][np]
+  uint32_t* part;          // [L * M * S]
+  const uint32_t* partoff; // [L * M * S]
+  int32_t* staged;
+  uint32_t np, M, ch, n_chunks, n_slices, slice_vecs;
+};
+
+// Block (t, chunk, slice): histogram of the keys of table t inside the chunk,
+// over the slice's rows, in LDS.
+__global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
+  extern __shared__ uint32_t h[];
+  const uint32_t sl = blockIdx.x % a.n_slices;
+  const uint32_t ck = (blockIdx.x / a.n_slices) % a.n_chunks;
+  const uint32_t t = blockIdx.x / (a.n_slices * a.n_chunks);
+  const uint32_t lo = ck * a.ch;
+  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads) h[j] = 0;
+  __syncthreads();
+  const uint4* rowv = reinterpret_cast<const uint4*>(a.keys_t + (uint64_t)t * a.np);
+  const uint32_t v0 = sl * a.slice_vecs;
+  uint32_t v1 = v0 + a.slice_vecs;
+  if (v1 > a.np / 4) v1 = a.np / 4;
+  for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
+    const uint4 x = rowv[v];
+    const uint32_t d0 = x.x - lo, d1 = x.y - lo, d2 = x.z - lo, d3 = x.w - lo;
+    if (d0 < a.ch) atomicAdd(&h[d0], 1u);
+    if (d1 < a.ch) atomicAdd(&h[d1], 1u);
+    if (d2 < a.ch) atomicAdd(&h[d2], 1u);
+    if (d3 < a.ch) atomicAdd(&h[d3], 1u);
+  }
+  __syncthreads();
+  const uint64_t b0 = (uint64_t)t * a.M + lo;
+  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads)
+    a.part[(b0 + j) * a.n_slices + sl] = h[j];
+}
+
+// Same blocks: each arrival's row id goes to the next free slot of its
+// (bucket, slice) run; LDS cursors start at partoff.
+__global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) {
+  extern __shared__ uint32_t cur[];
+  const uint32_t sl = blockIdx.x % a.n_slices;
+  const uint32_t ck = (blockIdx.x / a.n_slices) % a.n_chunks;
+  const uint32_t t = blockIdx.x / (a.n_slices * a.n_chunks);
+  const uint32_t lo = ck * a.ch;
+  const uint64_t b0 = (uint64_t)t * a.M + lo;
+  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads)
+    cur[j] = a.partoff[(b0 + j) * a.n_slices + sl];
+  __syncthreads();
+  const uint4* rowv = reinterpret_cast<const uint4*>(a.keys_t + (uint64_t)t * a.np);
+  const uint32_t v0 = sl * a.slice_vecs;
+  uint32_t v1 = v0 + a.slice_vecs;
+  if (v1 > a.np / 4) v1 = a.np / 4;
+  for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
+    const uint4 x = rowv[v];
+    const uint32_t kk[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t d = kk[j] - lo;
+      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(4 * v + (uint32_t)j);
+    }
+  }
+}
+
+// counts[b] = sum of the bucket's slice counts, seg[b] = its first staged slot.
+__global__ void bucket_totals_kernel(const uint32_t* part, const uint32_t* partoff, uint64_t nb,
+                                     uint32_t n_slices, uint32_t* counts, uint32_t* seg) {
+  for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
+       b += (uint64_t)gridDim.x * blockDim.x) {
+    uint32_t c = 0;
+    for (uint32_t s = 0; s < n_slices; ++s) c += part[b * n_slices + s];
+    counts[b] = c;
+    seg[b] = partoff[b * n_slices];
   }
 }
 
@@ -107,18 +198,6 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
   }
 }
 
-__global__ void insert_scatter_kernel(const uint32_t* __restrict__ keys,
-                                      const uint32_t* __restrict__ rank, uint32_t n_elems, uint32_t L,
-                                      uint32_t M, const uint32_t* __restrict__ seg,
-                                      int32_t* __restrict__ staged) {
-  for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < n_elems; e += gridDim.x * blockDim.x) {
-    const uint32_t r = rank[e];
-    if (r == kEmpty) continue;
-    const uint32_t k = keys[e];
-    staged[seg[(uint64_t)(e % L) * M + k] + r] = (int32_t)(e / L);
-  }
-}
-
 struct SelectArgs {
   const uint32_t* counts;
   const uint32_t* seg;
@@ -161,6 +240,21 @@ __global__ void bucket_select_small_kernel(SelectArgs a) {
   }
 }
 
+// Ascending sort of one 64-bit value per lane across the 64 lanes.
+__device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t o = (uint64_t)__shfl_xor((long long)v, (int)j, kWave);
+      const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+      v = (((lane & j) == 0) == ((lane & k) == 0)) ? mn : mx;
+    }
+  }
+  return v;
+}
+
 // One wave per worklist bucket.
 __global__ __launch_bounds__(64) void bucket_select_wave_kernel(SelectArgs a) {
   __shared__ uint64_t buf[kWaveCap];
@@ -176,6 +270,13 @@ __global__ __launch_bounds__(64) void bucket_select_wave_kernel(SelectArgs a) {
     const uint32_t t = bk / a.M;
     const uint32_t start = a.seg[bk];
     const int32_t* src = a.staged + start;
+    if (n <= (uint32_t)kWave) {
+      // one arrival per lane, bitonic sort across the wave in registers
+      const uint64_t v = lane < n ? priority(a.s_p, t, (uint32_t)src[lane]) : ~0ull;
+      const uint64_t sorted = wave_bitonic_sort(v);
+      if (lane < n && lane < R) a.ids[(uint64_t)bk * R + lane] = (int32_t)(uint32_t)sorted;
+      continue;
+    }
     uint32_t c;
     if (n <= sort_all) {
       c = n;
@@ -238,51 +339,97 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   return hipGetLastError();
 }
 
+namespace {
+
+// Shape of the LDS-privatised counting sort for n rows.
+struct Geo {
+  uint32_t np, ch, n_chunks, n_slices, slice_vecs;
+  uint64_t nb, nparts, tiles;
+};
+
+Geo geometry(const Cfg& c, int64_t n_rows) {
+  Geo g;
+  g.np = (uint32_t)(((uint64_t)(n_rows > 0 ? n_rows : 1) + 63) / 64 * 64);
+  g.ch = c.M < kChunk ? c.M : kChunk;
+  g.n_chunks = c.M / g.ch;
+  const uint32_t base_blocks = (uint32_t)c.L * g.n_chunks;
+  uint32_t s = (1024 + base_blocks - 1) / base_blocks;   // aim for ~1024 blocks
+  const uint32_t max_s = g.np / 16384 > 1 ? g.np / 16384 : 1;  // slices of >= 16384 rows
+  if (s > max_s) s = max_s;
+  if (s < 1) s = 1;
+  g.n_slices = s;
+  g.slice_vecs = (g.np / 4 + s - 1) / s;
+  g.nb = (uint64_t)c.L * c.M;
+  g.nparts = g.nb * s;
+  g.tiles = (g.nparts + kTile - 1) / kTile;
+  return g;
+}
+
+}  // namespace
+
 size_t insert_ws_bytes(const Cfg& c, int64_t n_rows) {
-  const uint64_t ne = (uint64_t)n_rows * c.L, nb = (uint64_t)c.L * c.M;
-  const uint64_t tiles = (nb + kTile - 1) / kTile;
-  return align256(4 * ne) * 2 + align256(4 * nb) * 2 + align256(4 * (tiles + 1)) + align256(4);
+  const Geo g = geometry(c, n_rows);
+  const uint64_t ne = (uint64_t)(n_rows > 0 ? n_rows : 1) * c.L;
+  return align256(4 * (uint64_t)c.L * g.np) + align256(4 * ne) + 2 * align256(4 * g.nparts) +
+         2 * align256(4 * g.nb) + align256(4 * (g.tiles + 1)) + align256(4);
 }
 
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
-  const uint64_t ne = (uint64_t)n_rows * c.L, nb = (uint64_t)c.L * c.M;
-  const uint64_t tiles = (nb + kTile - 1) / kTile;
+  const Geo g = geometry(c, n_rows);
+  const uint64_t ne = (uint64_t)(n_rows > 0 ? n_rows : 1) * c.L;
   char* p = (char*)ws;
   InsertWs w;
-  w.rank = (uint32_t*)p;
-  p += align256(4 * ne);
+  w.keys_t = (uint32_t*)p;
+  p += align256(4 * (uint64_t)c.L * g.np);
   w.staged = (int32_t*)p;
   p += align256(4 * ne);
+  w.part = (uint32_t*)p;
+  p += align256(4 * g.nparts);
+  w.partoff = (uint32_t*)p;
+  p += align256(4 * g.nparts);
   w.seg = (uint32_t*)p;
-  p += align256(4 * nb);
+  p += align256(4 * g.nb);
   w.worklist = (uint32_t*)p;
-  p += align256(4 * nb);
+  p += align256(4 * g.nb);
   w.tile_sums = (uint32_t*)p;
-  p += align256(4 * (tiles + 1));
+  p += align256(4 * (g.tiles + 1));
   w.wl_len = (uint32_t*)p;
   return w;
 }
 
 hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t* counts,
                          int32_t* ids, const InsertWs& w, hipStream_t s) {
-  const uint64_t nb = (uint64_t)c.L * c.M;
-  const uint32_t ne = (uint32_t)((uint64_t)n_rows * c.L);
+  const Geo g = geometry(c, n_rows);
   hipError_t e;
-  // initialisation: clear the counters (the reservoirs need no clearing)
-  if ((e = launch_fill_u32(counts, nb, 0u, s)) != hipSuccess) return e;
   if ((e = launch_fill_u32(w.wl_len, 1, 0u, s)) != hipSuccess) return e;
-  if (ne == 0) return hipSuccess;
-  hipLaunchKernelGGL(insert_count_kernel, dim3(grid_for(ne, 256, 16)), dim3(256), 0, s, keys, ne,
-                     (uint32_t)c.L, c.M, counts, w.rank);
-  const uint32_t tiles = (uint32_t)((nb + kTile - 1) / kTile);
-  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(tiles), dim3(kScanThreads), 0, s, counts, nb,
+  if (n_rows <= 0) return launch_fill_u32(counts, g.nb, 0u, s);
+  // table-major keys
+  hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
+                     (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t);
+  PartArgs pa;
+  pa.keys_t = w.keys_t;
+  pa.part = w.part;
+  pa.partoff = w.partoff;
+  pa.staged = w.staged;
+  pa.np = g.np;
+  pa.M = c.M;
+  pa.ch = g.ch;
+  pa.n_chunks = g.n_chunks;
+  pa.n_slices = g.n_slices;
+  pa.slice_vecs = g.slice_vecs;
+  const uint32_t blocks = (uint32_t)c.L * g.n_chunks * g.n_slices;
+  const size_t lds = sizeof(uint32_t) * g.ch;
+  hipLaunchKernelGGL(part_count_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
+  // exclusive scan of the (bucket, slice) counts
+  const uint32_t tiles = (uint32_t)g.tiles;
+  hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(tiles), dim3(kScanThreads), 0, s, w.part, g.nparts,
                      w.tile_sums);
-  hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, w.tile_sums,
-                     tiles);
-  hipLaunchKernelGGL(scan_tiles_kernel, dim3(tiles), dim3(kScanThreads), 0, s, counts, nb,
-                     w.tile_sums, w.seg);
-  hipLaunchKernelGGL(insert_scatter_kernel, dim3(grid_for(ne, 256, 16)), dim3(256), 0, s, keys,
-                     w.rank, ne, (uint32_t)c.L, c.M, w.seg, w.staged);
+  hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, w.tile_sums, tiles);
+  hipLaunchKernelGGL(scan_tiles_kernel, dim3(tiles), dim3(kScanThreads), 0, s, w.part, g.nparts,
+                     w.tile_sums, w.partoff);
+  hipLaunchKernelGGL(bucket_totals_kernel, dim3(grid_for(g.nb, 256, 16)), dim3(256), 0, s, w.part,
+                     w.partoff, g.nb, g.n_slices, counts, w.seg);
+  hipLaunchKernelGGL(part_scatter_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
   SelectArgs a;
   a.counts = counts;
   a.seg = w.seg;
@@ -290,11 +437,11 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.ids = ids;
   a.worklist = w.worklist;
   a.wl_len = w.wl_len;
-  a.n_buckets = nb;
+  a.n_buckets = g.nb;
   a.s_p = c.seeds.s_p;
   a.M = c.M;
   a.R = c.R;
-  hipLaunchKernelGGL(bucket_select_small_kernel, dim3(grid_for(nb, 256, 16)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_small_kernel, dim3(grid_for(g.nb, 256, 16)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_select_wave_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
   return hipGetLastError();
 }
