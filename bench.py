@@ -49,7 +49,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000,
                     help="queries the CPU oracle answers (the rest is extrapolated)")
-    ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "traffic.json"))
+    ap.add_argument("--traffic-table", default=os.path.join(ROOT, "profiles", "hbm_traffic.txt"),
+                    help="calibrated per-launch HBM bytes from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the benchmark, copy this many MiB device to device (a plain "
                          "copy kernel of known size that calibrates the HBM byte counters)")
@@ -148,16 +149,9 @@ def main():
     dom = max(("hash", "query"), key=lambda x: phases[x]["ms"])
     kernel = {"hash": "doph_hash_kernel", "query": "count_topk_kernel"}[dom]
     achieved = phases[dom]["alg_bytes"] / (phases[dom]["ms"] * 1e6)
-    traffic = None
-    try:
-        with open(args.traffic_json) as f:
-            tj = json.load(f)
-        ent = tj.get(args.workload, {}).get(kernel)
-        if ent and ent.get("source_sha") == _kernel_source_sha():
-            traffic = ent["bytes_per_launch"]
-    except (OSError, ValueError):
-        pass
-    roofline = {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+    traffic = _traffic(args.traffic_table, args.workload, kernel)
+    roofline = {"bound": "hbm", "kernel": kernel + (" (all table-size stages)" if dom == "query" else ""),
+                "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
 
@@ -201,6 +195,20 @@ def copy_calibration(mib):
     ms = ev[0].elapsed_time(ev[1])
     print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "ms": round(ms, 4),
                       "GBps": round(8 * n / (ms * 1e6), 1)}), flush=True)
+
+
+def _traffic(path, workload, kernel):
+    """Calibrated HBM bytes per launch for this kernel, or None if the table is
+    missing or was measured on different kernel sources."""
+    try:
+        with open(path) as f:
+            for line in f:
+                w = line.split()
+                if len(w) == 4 and not line.startswith("#") and w[0] == workload and w[1] == kernel:
+                    return int(w[3]) if w[2] == _kernel_source_sha() else None
+    except OSError:
+        pass
+    return None
 
 
 def _kernel_source_sha():
