@@ -43,6 +43,7 @@ struct QueryArgs {
   int64_t n_indexed;
   uint32_t M;
   int L, R, k, self_mode, cbits;
+  int r_aligned;              // R % 4 == 0: a task is one 16-byte load
   uint32_t max_total;         // candidates this launch's table accepts
   uint32_t sb;                // survivor buffer entries
 };
@@ -51,7 +52,7 @@ __host__ __device__ inline uint32_t slack_for(uint32_t need) { return need / 8 >
 
 __host__ __device__ inline size_t smem_bytes(int cap, int L, uint32_t sb) {
   const size_t scratch = sb > 256 ? sb : 256;
-  return (size_t)cap * 4 + scratch * 4 + (size_t)L * 12 + (size_t)(L + 1) * 4 + 16;
+  return (size_t)cap * 4 + scratch * 4 + (size_t)L * 16 + (size_t)(L + 1) * 4 + 16;
 }
 
 __device__ __forceinline__ uint32_t lane_id() { return threadIdx.x; }
@@ -84,22 +85,6 @@ __device__ __forceinline__ void tab_reg_add(uint32_t (&r)[LCH], uint32_t t, uint
     for (int i = 0; i < LCH; ++i)
       if ((uint32_t)i == c) r[i] += add;
   }
-}
-
-__device__ __forceinline__ uint32_t wave_incl_max(uint32_t v) {
-  const int lane = threadIdx.x & (kWave - 1);
-#pragma unroll
-  for (int d = 1; d < kWave; d <<= 1) {
-    const uint32_t o = __shfl_up(v, d, kWave);
-    if (lane >= d) v = v > o ? v : o;
-  }
-  return v;
-}
-
-__device__ __forceinline__ uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, kWave);
-  return v;
 }
 
 // Sort m <= 64 * KPL keys held in scratch (ascending) across the wave, KPL
@@ -136,7 +121,7 @@ __device__ __forceinline__ void sort_write(const uint32_t* scratch, uint32_t m, 
 #pragma unroll
         for (int r = 0; r < KPL; ++r) {
           const uint32_t i = lane * KPL + (uint32_t)r;
-          const uint32_t o = (uint32_t)__shfl_xor((int)x[r], (int)lj, kWave);
+          const uint32_t o = xor_lane(x[r], lj);
           const bool up = (i & kk) == 0, lower = (lane & lj) == 0;
           const uint32_t mn = x[r] < o ? x[r] : o, mx = x[r] < o ? o : x[r];
           x[r] = (lower == up) ? mn : mx;
@@ -199,17 +184,16 @@ __device__ __forceinline__ void rank_write(const uint32_t* scratch, uint32_t m, 
   }
 }
 
-template <int CAP, int LCH>
+template <int CAP, int LCH, bool ALIGNED>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
-  constexpr int U = 4;                 // candidates per lane per window
-  constexpr int W = kWave * U;         // window of the flattened candidate list
+  constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
+  constexpr int W = kWave * U;         // tasks per window
   constexpr int kLog = __builtin_ctz(CAP);
   extern __shared__ __align__(16) unsigned char smem[];
   uint32_t* tab = (uint32_t*)smem;                         // [CAP] packed (id << cbits | count)
   uint32_t* scratch = tab + CAP;                           // [max(W, sb)] window marks, then survivors
-  uint32_t* tpref = scratch + (a.sb > (uint32_t)W ? a.sb : (uint32_t)W);  // [L] table offsets
-  uint32_t* tbase = tpref + a.L;                           // [2 L] 64-bit slot bases (lo, hi)
-  uint32_t* hist = tbase + 2 * a.L;                        // [L + 1]
+  uint4* tinfo = reinterpret_cast<uint4*>(scratch + (a.sb > (uint32_t)W ? a.sb : (uint32_t)W));  // [L]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(tinfo + a.L);  // [L + 1]
 
   const uint32_t lane = lane_id();
   const uint32_t L = (uint32_t)a.L;
@@ -228,9 +212,14 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
 
-    // 1. occupancy and flattened offsets of the L buckets
-    uint32_t pref[LCH], nts[LCH];
-    uint32_t total = 0;
+    // 1. occupancy of the L buckets.  Each bucket's occupied slots are cut
+    // into tasks of 4 consecutive slots (one 16-byte load); one packed scan
+    // gives every table its first candidate (high half) and first task (low
+    // half).  tinfo[t] = {slot base - 4 * first task (64-bit), first task * 4
+    // + occupancy}, so task j of the query reads ids[base' + 4 j + i] for
+    // 4 j + i < end.
+    uint32_t tstart[LCH], tcnt[LCH];
+    uint32_t carry = 0;
 #pragma unroll
     for (int c = 0; c < LCH; ++c) {
       const uint32_t t = (uint32_t)c * 64 + lane;
@@ -245,16 +234,18 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
           base = bucket * R;
         }
       }
-      const uint32_t inc = wave_incl_scan(nt);
-      pref[c] = total + inc - nt;
-      nts[c] = nt;
-      if (t < L) {
-        tpref[t] = pref[c];
-        tbase[2 * t] = (uint32_t)base;
-        tbase[2 * t + 1] = (uint32_t)(base >> 32);
-      }
-      total += rl(inc, 63);
+      const uint32_t ct = (nt + 3) >> 2;
+      const uint32_t packed = (nt << 16) | ct;
+      const uint32_t inc = wave_incl_scan(packed);
+      const uint32_t pre = carry + inc - packed;
+      tstart[c] = pre & 0xFFFFu;
+      tcnt[c] = ct;
+      if (t < L)
+        tinfo[t] = make_uint4((uint32_t)(base - 4ull * tstart[c]), (uint32_t)((base - 4ull * tstart[c]) >> 32),
+                              4u * tstart[c] + nt, 0u);
+      carry += rl(inc, 63);
     }
+    const uint32_t total = carry >> 16, n_tasks = carry & 0xFFFFu;
     if (total > a.max_total) {
       if (lane == 0) a.ovf_list[atomicAdd(a.ovf_len, 1u)] = (uint32_t)q;
       continue;
@@ -262,61 +253,76 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     for (uint32_t c = lane; c <= L; c += kWave) hist[c] = 0;
     __syncthreads();
 
-    // 2-3. gather and count, one window of W candidates at a time
-    for (uint32_t base = 0; base < total; base += W) {
-      // mark where each non-empty table starts inside the window; the table
-      // holding the window's first candidate is marked at position 0
+    // 2-3. gather and count, W tasks (4 W candidates) per window
+    for (uint32_t base = 0; base < n_tasks; base += W) {
+      // mark where each table's tasks start inside the window; the table
+      // holding the window's first task is marked at position 0
       uint32_t tf = 0;
 #pragma unroll
       for (int c = 0; c < LCH; ++c) {
         const uint32_t t = (uint32_t)c * 64 + lane;
-        const bool ne = nts[c] > 0;
-        if (ne && pref[c] > base && pref[c] < base + W) scratch[pref[c] - base] = t;
-        const uint64_t bal = __ballot(ne && pref[c] <= base);
+        const bool ne = tcnt[c] > 0;
+        if (ne && tstart[c] > base && tstart[c] < base + W) scratch[tstart[c] - base] = t;
+        const uint64_t bal = __ballot(ne && tstart[c] <= base);
         if (bal) tf = (uint32_t)c * 64 + 63 - (uint32_t)__clzll((long long)bal);
       }
       if (lane == 0) scratch[0] = tf;
       __syncthreads();
-      uint32_t carry = 0;
-      uint32_t id[U];
-      bool pend[U];
+      uint32_t tcarry = 0;
+      uint4 ids4[U];
+      uint32_t vmask[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t mk = scratch[u * kWave + lane];
         scratch[u * kWave + lane] = kEmpty;
-        uint32_t t = wave_incl_max(mk == kEmpty ? 0u : mk + 1);  // 0 = no mark yet
-        t = t > carry ? t : carry;
-        carry = rl(t, 63);
-        const uint32_t e = base + (uint32_t)u * kWave + lane;
-        pend[u] = e < total;
-        id[u] = 0;
-        if (pend[u]) {
-          const uint32_t tt = t - 1;
-          const uint64_t sb = ((uint64_t)tbase[2 * tt + 1] << 32) | tbase[2 * tt];
-          id[u] = (uint32_t)a.ids[sb + (e - tpref[tt])];
+        uint32_t tt = wave_incl_max(mk == kEmpty ? 0u : mk + 1);  // 0 = no mark yet
+        tt = tt > tcarry ? tt : tcarry;
+        tcarry = rl(tt, 63);
+        // every lane loads: a lane past the last task reads the last task
+        // again (always in bounds) and masks all four candidates off
+        const uint32_t task = base + (uint32_t)u * kWave + lane;
+        const uint32_t tc = task < n_tasks ? task : n_tasks - 1;
+        const uint4 ti = tinfo[tt - 1];
+        const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
+        const uint32_t room = ti.z - 4u * tc;  // occupied slots of this bucket from here, >= 1
+        vmask[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
+        if (ALIGNED) {
+          ids4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
+        } else {
+          const uint32_t last = room - 1;
+          ids4[u].x = (uint32_t)a.ids[addr];
+          ids4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
+          ids4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
+          ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
         }
       }
-      uint32_t slot[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        pend[u] = pend[u] && (int64_t)id[u] != self;
-        slot[u] = (id[u] * 0x9E3779B1u) >> (32 - kLog);
-      }
-      while (pend[0] || pend[1] || pend[2] || pend[3]) {
-        uint32_t old[U];
+        const uint32_t id[4] = {ids4[u].x, ids4[u].y, ids4[u].z, ids4[u].w};
+        bool pend[4];
+        uint32_t slot[4];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-          old[u] = pend[u] ? atomicCAS(&tab[slot[u]], kEmpty, (id[u] << cb) | 1u) : 0u;
+        for (int j = 0; j < 4; ++j) {
+          pend[j] = ((vmask[u] >> j) & 1u) && (int64_t)id[j] != self;
+          slot[j] = (id[j] * 0x9E3779B1u) >> (32 - kLog);
+        }
+        // linear probing (measured faster here than triangular probing)
+        while (pend[0] || pend[1] || pend[2] || pend[3]) {
+          uint32_t old[4];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-          if (!pend[u]) continue;
-          if (old[u] == kEmpty) {
-            pend[u] = false;
-          } else if ((old[u] >> cb) == id[u]) {
-            atomicAdd(&tab[slot[u]], 1u);
-            pend[u] = false;
-          } else {
-            slot[u] = (slot[u] + 1) & (CAP - 1);
+          for (int j = 0; j < 4; ++j)
+            old[j] = pend[j] ? atomicCAS(&tab[slot[j]], kEmpty, (id[j] << cb) | 1u) : 0u;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (!pend[j]) continue;
+            if (old[j] == kEmpty) {
+              pend[j] = false;
+            } else if ((old[j] >> cb) == id[j]) {
+              atomicAdd(&tab[slot[j]], 1u);
+              pend[j] = false;
+            } else {
+              slot[j] = (slot[j] + 1) & (CAP - 1);
+            }
           }
         }
       }
@@ -377,7 +383,7 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
         // guessed from the uniform spread of ids, then bisected
         const uint64_t span = (uint64_t)a.n_indexed;
         uint64_t lo = 0, hi = span;
-        uint64_t g = ((uint64_t)(need + slack / 2) * span) / ties + 1;
+        uint64_t g = (uint64_t)((float)(need + slack / 2) * ((float)span / (float)ties)) + 1;
         if (g >= hi) g = hi - 1;
         if (g <= lo) g = lo + 1;
         for (int it = 0; it < 64; ++it) {
@@ -438,17 +444,23 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   }
 }
 
-template <int CAP, int LCH>
-hipError_t launch_cap(const QueryArgs& a, int grid, hipStream_t st) {
+template <int CAP, int LCH, bool ALIGNED>
+hipError_t launch_kernel(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = smem_bytes(CAP, a.L, a.sb);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
   if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH>),
-                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH, ALIGNED>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((count_topk_kernel<CAP, LCH>), dim3(grid), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((count_topk_kernel<CAP, LCH, ALIGNED>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError();
+}
+
+template <int CAP, int LCH>
+hipError_t launch_cap(const QueryArgs& a, int grid, hipStream_t st) {
+  return a.r_aligned ? launch_kernel<CAP, LCH, true>(a, grid, st) : launch_kernel<CAP, LCH, false>(a, grid, st);
 }
 
 template <int LCH>
@@ -516,6 +528,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   a.k = k;
   a.self_mode = self_mode;
   a.cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
+  a.r_aligned = (c.R % 4) == 0 && (((uintptr_t)ids) & 15) == 0;
 
   const uint32_t full = (uint32_t)c.L * (uint32_t)c.R;  // most candidates a query can have
   uint32_t last = 1024;
@@ -537,7 +550,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   caps[n_stage++] = (int)last;
 
   const int cus = device_info().cus;
-  const int per_cu = env_int("FLASH_QUERY_BLOCKS_PER_CU", 32);
+  const int per_cu = env_int("FLASH_QUERY_BLOCKS_PER_CU", 128);
   hipError_t e;
   if (n_stage > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
   for (int s = 0; s < n_stage; ++s) {
@@ -546,6 +559,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     b.max_total = final_stage ? full : (uint32_t)caps[s] * 3 / 4;
     const uint32_t need_sb = (uint32_t)k + slack_for((uint32_t)k);
     b.sb = need_sb < b.max_total ? need_sb : (b.max_total > (uint32_t)k ? b.max_total : (uint32_t)k);
+    b.sb = (b.sb + 3) & ~3u;  // keeps tinfo 16-byte aligned
     if (s > 0) {
       b.qlist = w.ovf_list[(s - 1) & 1];
       b.qlist_len = w.ovf_len + ((s - 1) & 1);

@@ -247,7 +247,7 @@ __device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
   for (uint32_t k = 2; k <= 64; k <<= 1) {
 #pragma unroll
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t o = (uint64_t)__shfl_xor((long long)v, (int)j, kWave);
+      const uint64_t o = xor_lane64(v, j);
       const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
       v = (((lane & j) == 0) == ((lane & k) == 0)) ? mn : mx;
     }

@@ -387,3 +387,34 @@ def test_url_shaped_graph(fl, orc):
     okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(5, 32, 3, 64, seed=1), rp, ci, 64)
     occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 32, 1 << 15, 64)
     assert np.array_equal(i32(oi), wi) and np.array_equal(i32(oc), wc)
+
+
+def test_webspam_full_size_graph(fl, orc):
+    # The benchmark's workload and launch shape: 350,000 rows, ~1.3G nonzeros.
+    # Tables are compared in full; k-NN lists on 3,000 sampled queries (the
+    # oracle answers them one by one against its own full index).
+    import torch
+    from paper_1709_01190_amd import datagen
+    say("webspam-shaped full size graph")
+    spec = datagen.WEBSPAM
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    n = spec.n_rows
+    K, L, b, R, k = 4, 64, 4, 128, 128
+    p = fl.flash_params.make(K, L, b, R, seed=1)
+    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
+    gkeys = torch.empty(n * L, dtype=torch.int32, device="cuda")
+    fl.flash_hash(p, rp_d, ci_d, gkeys)
+    torch.cuda.synchronize()
+    rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
+    del rp_d, ci_d
+    op = orc.params(K, L, b, R, seed=1)
+    okeys = orc.doph(op, rp, ci)
+    assert np.array_equal(u32(gkeys).reshape(n, L), okeys)
+    ocounts, oids = orc.build_tables(op, okeys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
+    rng = np.random.default_rng(77)
+    sample = np.sort(rng.choice(n, size=3000, replace=False))
+    wi, wc = orc.query(op, ocounts, oids, okeys[sample], k, self_ids=sample.astype(np.int32))
+    gi = i32(oi)[sample]
+    gc = i32(oc)[sample]
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
