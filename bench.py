@@ -44,7 +44,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
+                    help="serving: offered queries per second, comma separated")
+    ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
+    ap.add_argument("--recall-queries", type=int, default=1000,
+                    help="serving: sampled queries scored against brute-force Jaccard")
     ap.add_argument("--rows", type=int, default=0, help="override the row count (parity/debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000,
@@ -57,6 +62,12 @@ def main():
     args = ap.parse_args()
     if args.copy_mib:
         copy_calibration(args.copy_mib)
+        return
+    if args.workload == "serving":
+        if args.gpus != 1:
+            print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
+            sys.exit(2)
+        serving_bench(args)
         return
 
     if args.gpus != 1:
@@ -179,6 +190,130 @@ def main():
         "phases": phases,
     }
     print(json.dumps(out), flush=True)
+
+
+def serving_bench(args):
+    """p50/p99 latency and throughput of the continuous-batching server against
+    plain batch-all, on a resident URL-shaped index (2.4M rows; K=5 L=32 b=3
+    R=64), with Poisson arrivals of batches of 1..4096 URL-shaped queries and
+    k in {10, 50, 200}."""
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import datagen, flash, serving
+
+    torch.cuda.set_device(0)
+    spec = datagen.URL
+    t0 = time.time()
+    rp, ci = datagen.make_rows(spec, 1, device="cuda")
+    p = flash.flash_params.make(5, 32, 3, 64, seed=1)
+    counts, ids = flash.alloc_index(p)
+    ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
+    flash.flash_build_index(p, rp, ci, counts, ids, ws)
+    torch.cuda.synchronize()
+    del ws
+    log(f"url-shaped index: {spec.n_rows} rows, {int(ci.numel())} nnz, built in {time.time() - t0:.1f}s")
+    # a pool of query rows (seed 2); each request takes a random slice of it
+    pool_n = 400_000
+    qrp_d, qci_d = datagen.make_rows(datagen.scaled(spec, pool_n), 2, device="cuda")
+    qrp, qci = qrp_d.cpu().numpy(), qci_d.cpu().numpy()
+    del qrp_d, qci_d
+
+    def rows(n, seed):
+        st = np.random.default_rng(seed).integers(0, pool_n - n + 1)
+        a, b = int(qrp[st]), int(qrp[st + n])
+        return (qrp[st:st + n + 1] - a).astype(np.int64), qci[a:b].copy()
+
+    ex = serving.GpuExecutor(p, counts, ids, spec.n_rows)
+    budget = 4 << 30
+    cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=8)
+    batch = serving.BatchAllServer(ex, budget_bytes=budget)
+    warm = serving.make_requests(rows, 50, qps=5e5, seed=99)
+    cont.run(warm)
+    batch.run(serving.make_requests(rows, 50, qps=5e5, seed=99))
+    torch.cuda.synchronize()
+    table = []
+    for rate in [float(x) for x in args.rates.split(",")]:
+        reqs = serving.make_requests(rows, args.requests, qps=rate, seed=int(rate) % 100_003)
+        c = cont.run(reqs)
+        c_lists = [(r.out_ids, r.out_counts) for r in reqs]
+        reqs2 = serving.make_requests(rows, args.requests, qps=rate, seed=int(rate) % 100_003)
+        b = batch.run(reqs2)
+        same = all(np.array_equal(x[0], r.out_ids) and np.array_equal(x[1], r.out_counts)
+                   for x, r in zip(c_lists, reqs2) if not r.rejected)
+        row = {"offered_qps": rate, "continuous": {k2: round(v, 3) for k2, v in c.items()},
+               "batch_all": {k2: round(v, 3) for k2, v in b.items()}, "identical_lists": bool(same)}
+        log(json.dumps(row))
+        table.append(row)
+    recall = None
+    if args.recall_queries > 0:
+        import oracle
+        rng = np.random.default_rng(3)
+        sel = np.sort(rng.choice(pool_n, size=args.recall_queries, replace=False))
+        k = 50
+        srp = np.concatenate([[0], np.cumsum(qrp[sel + 1] - qrp[sel])]).astype(np.int64)
+        sci = np.concatenate([qci[qrp[i]:qrp[i + 1]] for i in sel]).astype(np.int32)
+        oi = torch.empty(len(sel) * k, dtype=torch.int32, device="cuda")
+        oc = torch.empty_like(oi)
+        qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=len(sel), k=k)
+        flash.flash_query_batch(p, counts, ids, spec.n_rows, torch.from_numpy(srp).cuda(),
+                                torch.from_numpy(sci).cuda(), k, oi, oc, qws)
+        torch.cuda.synchronize()
+        found = oi.cpu().numpy().reshape(len(sel), k)
+        recall = _recall_against_index(oracle, rp.cpu().numpy(), ci.cpu().numpy(), spec.n_cols, srp, sci,
+                                       found)
+        log(f"R@{k} over {len(sel)} sampled queries: {recall}")
+    top = max(table, key=lambda r: r["offered_qps"]) if table else None
+    out = {
+        "metric": "serving p99 latency (url-shape index, continuous batching)",
+        "value": top["continuous"]["p99_ms"] if top else None,
+        "unit": "ms",
+        "n_gpus": 1,
+        "higher_is_better": False,
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "url-shaped serving", "index_rows": spec.n_rows, "K": 5, "L": 32,
+                   "bits_per_hash": 3, "R": 64, "k": [10, 50, 200], "batch": [1, 4096],
+                   "requests_per_rate": args.requests, "hbm_budget_bytes": budget, "slots": 8},
+        "rates": table,
+        "recall": recall,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def _recall_against_index(oracle, rp, ci, n_cols, qrp, qci, found):
+    """R@k of external queries against brute-force exact Jaccard over the
+    indexed rows: append the queries to the row set and score them."""
+    import numpy as np
+    n = rp.shape[0] - 1
+    rp2 = np.concatenate([rp, qrp[1:] + rp[-1]])
+    ci2 = np.concatenate([ci, qci])
+    qids = np.arange(n, n + qrp.shape[0] - 1, dtype=np.int64)
+    # the best indexed row: the first indexed id in each query's exact top-8
+    # (other queries, appended above, are skipped)
+    top, ti, tu = oracle.jaccard_knn(rp2, ci2, n_cols, qids, 8)
+    pick = np.argmax((top >= 0) & (top < n), axis=1)
+    rows_ = np.arange(top.shape[0])
+    best = np.where(((top >= 0) & (top < n)).any(axis=1), top[rows_, pick], -1)[:, None]
+    bi = ti[rows_, pick][:, None]
+    bu = tu[rows_, pick][:, None]
+    # queries must not match each other: rescore only against indexed rows
+    xs = np.repeat(qids, found.shape[1])
+    ys = found.reshape(-1).astype(np.int64)
+    ok = ys >= 0
+    inter = np.zeros(xs.shape[0], np.int64)
+    uni = np.ones(xs.shape[0], np.int64)
+    if ok.any():
+        a, b = oracle.jaccard_pairs(rp2, ci2, xs[ok], ys[ok])
+        inter[ok], uni[ok] = a, b
+    inter = inter.reshape(found.shape)
+    uni = uni.reshape(found.shape)
+    scored = (best[:, 0] >= 0) & (best[:, 0] < n)
+    hit = ((inter * bu[:, :1] == bi[:, :1] * uni) & (inter > 0)).any(axis=1) & scored
+    m = int(scored.sum())
+    return {"R_at_k": round(float(hit.sum()) / m, 4) if m else None, "k": int(found.shape[1]),
+            "scored_queries": m, "gold": "exact Jaccard"}
 
 
 def copy_calibration(mib):

@@ -62,7 +62,7 @@ extern "C" {
 
 /* Method parameters (Sec. 2.2, Sec. 4.4.1).  Limits checked by every call:
  * 1 <= K, 1 <= L <= 256, 1 <= bits_per_hash, K * bits_per_hash <= 30,
- * K * L <= 4096 (DOPH bins), 1 <= R <= 1024, L * R <= 8192,
+ * K * L <= 4096 (DOPH bins), 1 <= R <= 1024, L * R <= 8192, L * 2^(K * b) < 2^32,
  * 0 <= densify_attempts <= 65535, reserved == 0. */
 typedef struct flash_params {
     int32_t K;                /* minhashes per table key (meta-hash width)      */
@@ -143,6 +143,29 @@ FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, c
                                 const int32_t *self_ids, int32_t k, int32_t *out_ids,
                                 int32_t *out_counts, void *workspace, size_t workspace_bytes,
                                 void *stream);
+
+/* Alg. 3 for a batch whose queries want different k (batched uneven
+ * queries).  As flash_query_keys, except that query q returns its first
+ * k_per_query[q] ids (device int32[n_queries]; values are clamped to
+ * [1, k_max]) and its output row, of stride k_max, is padded with (-1, 0)
+ * after them.  1 <= k_max <= 1024.  Workspace: FLASH_OP_QUERY_KEYS. */
+FLASH_API int flash_query_keys_mixed(const flash_params *p, const uint32_t *counts,
+                                     const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+                                     const uint32_t *qkeys, const int32_t *self_ids,
+                                     const int32_t *k_per_query, int32_t k_max, int32_t *out_ids,
+                                     int32_t *out_counts, void *workspace, size_t workspace_bytes,
+                                     void *stream);
+
+/* flash_query_batch with a k per query: CSR queries are hashed into the
+ * workspace, then answered as flash_query_keys_mixed.  Workspace:
+ * FLASH_OP_QUERY. */
+FLASH_API int flash_query_batch_mixed(const flash_params *p, const uint32_t *counts,
+                                      const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+                                      int64_t nnz, const int64_t *q_row_ptr,
+                                      const int32_t *q_col_idx, const int32_t *self_ids,
+                                      const int32_t *k_per_query, int32_t k_max, int32_t *out_ids,
+                                      int32_t *out_counts, void *workspace, size_t workspace_bytes,
+                                      void *stream);
 
 /* Sec. 1 / Sec. 4.3: approximate k-NN graph.  Builds the index of all rows
  * into counts/ids, then queries every row with its own keys, leaving the row

@@ -42,7 +42,8 @@ struct QueryArgs {
   int64_t n_queries;
   int64_t n_indexed;
   uint32_t M;
-  int L, R, k, self_mode, cbits;
+  int L, R, k, self_mode, cbits;   // k: the row stride of the outputs (the largest k)
+  const int32_t* k_per_query;       // per-query k (clamped to [1, k]) if not null
   int r_aligned;              // R % 4 == 0: a task is one 16-byte load
   uint32_t max_total;         // candidates this launch's table accepts
   uint32_t sb;                // survivor buffer entries
@@ -200,7 +201,7 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   const uint32_t R = (uint32_t)a.R;
   const uint32_t cb = (uint32_t)a.cbits;
   const uint32_t cmask = (1u << cb) - 1u;
-  const uint32_t k = (uint32_t)a.k;
+  const uint32_t kmax = (uint32_t)a.k;
   const uint32_t idshift = 32u - cb;   // survivor key = (L - count) << idshift | id
   uint4* tab4 = reinterpret_cast<uint4*>(tab);
   for (uint32_t i = lane; i < (uint32_t)CAP / 4; i += kWave) tab4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
@@ -211,6 +212,11 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
     const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
+    uint32_t k = kmax;
+    if (a.k_per_query) {
+      const int32_t kk = a.k_per_query[q];
+      k = kk < 1 ? 1u : ((uint32_t)kk > kmax ? kmax : (uint32_t)kk);
+    }
 
     // 1. occupancy of the L buckets.  Each bucket's occupied slots are cut
     // into tasks of 4 consecutive slots (one 16-byte load); one packed scan
@@ -427,7 +433,11 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     }
     if (m > a.sb) m = a.sb;
     __syncthreads();
-    const uint64_t orow = q * (uint64_t)k;
+    const uint64_t orow = q * (uint64_t)kmax;
+    for (uint32_t j = k + lane; j < kmax; j += kWave) {
+      a.out_ids[orow + j] = -1;
+      a.out_counts[orow + j] = 0;
+    }
     const uint32_t idmask = (idshift >= 32) ? 0xFFFFFFFFu : ((1u << idshift) - 1u);
     if (m <= 64) {
       sort_write<1>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
@@ -510,8 +520,8 @@ QueryWs query_ws_carve(const Cfg&, int64_t n_queries, void* ws) {
 // table at <= 3/4 load (the last takes every query) and hands the rest on.
 hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
                         int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
-                        const int32_t* self_ids, int self_mode, int32_t k, int32_t* out_ids,
-                        int32_t* out_counts, const QueryWs& w, hipStream_t st) {
+                        const int32_t* self_ids, int self_mode, int32_t k, const int32_t* k_per_query,
+                        int32_t* out_ids, int32_t* out_counts, const QueryWs& w, hipStream_t st) {
   if (n_queries <= 0) return hipSuccess;
   QueryArgs a = {};
   a.counts = counts;
@@ -527,6 +537,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   a.R = c.R;
   a.k = k;
   a.self_mode = self_mode;
+  a.k_per_query = k_per_query;
   a.cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
   a.r_aligned = (c.R % 4) == 0 && (((uintptr_t)ids) & 15) == 0;
 

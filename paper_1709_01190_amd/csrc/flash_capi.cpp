@@ -34,6 +34,8 @@ int make_cfg(const flash_params* p, Cfg* c) {
   if ((int64_t)p->K * p->L > 4096) return fail(FLASH_ENOTIMPL, "K * L > 4096 bins is not supported");
   if (p->R > 1024) return fail(FLASH_ENOTIMPL, "R > 1024 is not supported");
   if ((int64_t)p->L * p->R > 8192) return fail(FLASH_ENOTIMPL, "L * R > 8192 is not supported");
+  if (((uint64_t)p->L << (p->K * p->bits_per_hash)) > 0xFFFFFFFFull)
+    return fail(FLASH_ENOTIMPL, "L * 2^(K * bits_per_hash) buckets must be < 2^32");
   if (p->densify_attempts < 0 || p->densify_attempts > 65535)
     return fail(FLASH_EINVAL, "densify_attempts must be in [0, 65535]");
   c->K = p->K;
@@ -207,7 +209,7 @@ FLASH_API int flash_query_keys(const flash_params* p, const uint32_t* counts, co
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY_KEYS)");
   const QueryWs w = query_ws_carve(c, n_queries, workspace);
   hipError_t e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
-                              k, out_ids, out_counts, w, (hipStream_t)stream);
+                              k, nullptr, out_ids, out_counts, w, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
@@ -234,7 +236,54 @@ FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, c
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
   e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k,
-                   out_ids, out_counts, w, s);
+                   nullptr, out_ids, out_counts, w, s);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API int flash_query_keys_mixed(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                                     int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
+                                     const int32_t* self_ids, const int32_t* k_per_query, int32_t k_max,
+                                     int32_t* out_ids, int32_t* out_counts, void* workspace,
+                                     size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_query(c, n_indexed, n_queries, k_max))) return r;
+  if (n_queries > 0 && (!counts || !ids || !qkeys || !out_ids || !out_counts || !k_per_query))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t need = query_ws_bytes(c, n_queries);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY_KEYS)");
+  const QueryWs w = query_ws_carve(c, n_queries, workspace);
+  hipError_t e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
+                              k_max, k_per_query, out_ids, out_counts, w, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API int flash_query_batch_mixed(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                                      int64_t n_indexed, int64_t n_queries, int64_t nnz,
+                                      const int64_t* q_row_ptr, const int32_t* q_col_idx,
+                                      const int32_t* self_ids, const int32_t* k_per_query,
+                                      int32_t k_max, int32_t* out_ids, int32_t* out_counts,
+                                      void* workspace, size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_query(c, n_indexed, n_queries, k_max))) return r;
+  if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
+  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts || !k_per_query))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t kb = keys_bytes(c, n_queries);
+  const size_t need = kb + query_ws_bytes(c, n_queries);
+  if (!workspace || workspace_bytes < need)
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY)");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* qkeys = (uint32_t*)workspace;
+  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
+  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k_max,
+                   k_per_query, out_ids, out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
@@ -262,7 +311,7 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   e = launch_insert(c, n_rows, keys, counts, ids, insert_ws_carve(c, n_rows, rest), s);
   if (e != hipSuccess) return hip_fail(e, "reservoir_insert");
-  e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, out_ids, out_counts,
+  e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, nullptr, out_ids, out_counts,
                    query_ws_carve(c, n_rows, rest), s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }

@@ -33,9 +33,9 @@ struct InsertWs {
   uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)
   uint32_t* partoff;    // [L * M * S]    exclusive prefix of part
   uint32_t* seg;        // [L * M]        first staged slot of each bucket
-  uint32_t* worklist;   // [L * M]        buckets for the wave-level select
+  uint4* work;          // [L * M]        {bucket, start, size} for the wave-level selects
   uint32_t* tile_sums;  // [tiles + 1]    scan carries
-  uint32_t* wl_len;     // [1]
+  uint32_t* wl_len;     // [2]
 };
 size_t insert_ws_bytes(const Cfg& c, int64_t n_rows);
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws);
@@ -52,8 +52,8 @@ QueryWs query_ws_carve(const Cfg& c, int64_t n_queries, void* ws);
 // self_mode: 0 = none, 1 = self_ids array, 2 = query index is its own id
 hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
                         int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
-                        const int32_t* self_ids, int self_mode, int32_t k, int32_t* out_ids,
-                        int32_t* out_counts, const QueryWs& w, hipStream_t s);
+                        const int32_t* self_ids, int self_mode, int32_t k, const int32_t* k_per_query,
+                        int32_t* out_ids, int32_t* out_counts, const QueryWs& w, hipStream_t s);
 
 // ---- misc
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);

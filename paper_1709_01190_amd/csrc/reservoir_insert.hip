@@ -203,40 +203,56 @@ struct SelectArgs {
   const uint32_t* seg;
   const int32_t* staged;
   int32_t* ids;
-  uint32_t* worklist;
-  uint32_t* wl_len;
+  uint4* work;          // [nb] {bucket, first staged slot, arrivals, 0}: mid-size
+                        // buckets from the front, large buckets from the back
+  uint32_t* wl_len;     // [2] mid-size and large bucket counts
   uint64_t n_buckets;
   uint64_t s_p;
   uint32_t M;
   int R;
 };
 
-// Buckets with at most kSmall arrivals: rank each arrival against the others
-// in registers.  Larger buckets go to the wave-level worklist.
-__global__ void bucket_select_small_kernel(SelectArgs a) {
-  for (uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; bk < a.n_buckets;
-       bk += (uint64_t)gridDim.x * blockDim.x) {
-    const uint32_t n = a.counts[bk];
-    if (n == 0) continue;
-    if (n > (uint32_t)kSmall) {
-      const uint32_t pos = atomicAdd(a.wl_len, 1u);
-      a.worklist[pos] = (uint32_t)bk;
-      continue;
-    }
-    const uint32_t t = (uint32_t)(bk / a.M);
-    const uint32_t start = a.seg[bk];
-    uint64_t pk[kSmall];
+constexpr uint32_t kMid = 64;  // arrivals handled by one wave in registers
+
+// Appends for the lanes where pred holds, with one atomic per wave; returns
+// each such lane's slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if ((threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
+  return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Thread per bucket.  Buckets with at most kSmall arrivals: rank each arrival
+// against the others in registers.  Larger buckets are listed for the
+// wave-level kernels, with their start and size so those need no lookup.
+__global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
+  const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = bk < a.n_buckets;
+  const uint32_t n = in ? a.counts[bk] : 0u;
+  const uint32_t start = in ? a.seg[bk] : 0u;
+  const bool mid = n > (uint32_t)kSmall && n <= kMid;
+  const bool big = n > kMid;
+  const uint32_t pm = wave_append(&a.wl_len[0], mid);
+  const uint32_t pb = wave_append(&a.wl_len[1], big);
+  if (mid) a.work[pm] = make_uint4((uint32_t)bk, start, n, 0u);
+  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, 0u);
+  if (n == 0 || n > (uint32_t)kSmall) return;
+  const uint32_t t = (uint32_t)(bk / a.M);
+  uint64_t pk[kSmall];
 #pragma unroll
-    for (int i = 0; i < kSmall; ++i)
-      pk[i] = (uint32_t)i < n ? priority(a.s_p, t, (uint32_t)a.staged[start + i]) : ~0ull;
+  for (int i = 0; i < kSmall; ++i)
+    pk[i] = (uint32_t)i < n ? priority(a.s_p, t, (uint32_t)a.staged[start + i]) : ~0ull;
 #pragma unroll
-    for (int i = 0; i < kSmall; ++i) {
-      if ((uint32_t)i >= n) break;
-      int r = 0;
+  for (int i = 0; i < kSmall; ++i) {
+    if ((uint32_t)i >= n) break;
+    int r = 0;
 #pragma unroll
-      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i];
-      if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
-    }
+    for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i];
+    if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
   }
 }
 
@@ -255,28 +271,37 @@ __device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
   return v;
 }
 
-// One wave per worklist bucket.
-__global__ __launch_bounds__(64) void bucket_select_wave_kernel(SelectArgs a) {
+// One wave per mid-size bucket (kSmall < n <= 64): one arrival per lane,
+// bitonic sort across the wave in registers; no LDS, so occupancy is high.
+__global__ __launch_bounds__(256) void bucket_select_mid_kernel(SelectArgs a) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t len = a.wl_len[0];
+  const uint32_t R = (uint32_t)a.R;
+  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
+  for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6); w < len; w += waves) {
+    const uint4 e = a.work[w];
+    const uint32_t bk = e.x, n = e.z;
+    const uint32_t t = bk / a.M;
+    const uint64_t v = lane < n ? priority(a.s_p, t, (uint32_t)a.staged[e.y + lane]) : ~0ull;
+    const uint64_t sorted = wave_bitonic_sort(v);
+    if (lane < n && lane < R) a.ids[(uint64_t)bk * R + lane] = (int32_t)(uint32_t)sorted;
+  }
+}
+
+// One wave per large bucket (n > 64).
+__global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
   __shared__ uint64_t buf[kWaveCap];
   __shared__ uint32_t cnt_sh;
   const uint32_t lane = threadIdx.x;
-  const uint32_t len = *a.wl_len;
+  const uint32_t len = a.wl_len[1];
   const uint32_t R = (uint32_t)a.R;
   const uint32_t sort_all = (2 * R > 256u ? 2 * R : 256u) < kWaveCap ? (2 * R > 256u ? 2 * R : 256u)
                                                                        : kWaveCap;
   for (uint32_t w = blockIdx.x; w < len; w += gridDim.x) {
-    const uint32_t bk = a.worklist[w];
-    const uint32_t n = a.counts[bk];
+    const uint4 e = a.work[a.n_buckets - 1 - w];
+    const uint32_t bk = e.x, n = e.z;
     const uint32_t t = bk / a.M;
-    const uint32_t start = a.seg[bk];
-    const int32_t* src = a.staged + start;
-    if (n <= (uint32_t)kWave) {
-      // one arrival per lane, bitonic sort across the wave in registers
-      const uint64_t v = lane < n ? priority(a.s_p, t, (uint32_t)src[lane]) : ~0ull;
-      const uint64_t sorted = wave_bitonic_sort(v);
-      if (lane < n && lane < R) a.ids[(uint64_t)bk * R + lane] = (int32_t)(uint32_t)sorted;
-      continue;
-    }
+    const int32_t* src = a.staged + e.y;
     uint32_t c;
     if (n <= sort_all) {
       c = n;
@@ -371,7 +396,7 @@ size_t insert_ws_bytes(const Cfg& c, int64_t n_rows) {
   const Geo g = geometry(c, n_rows);
   const uint64_t ne = (uint64_t)(n_rows > 0 ? n_rows : 1) * c.L;
   return align256(4 * (uint64_t)c.L * g.np) + align256(4 * ne) + 2 * align256(4 * g.nparts) +
-         2 * align256(4 * g.nb) + align256(4 * (g.tiles + 1)) + align256(4);
+         align256(4 * g.nb) + align256(16 * g.nb) + align256(4 * (g.tiles + 1)) + align256(8);
 }
 
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
@@ -389,8 +414,8 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
   p += align256(4 * g.nparts);
   w.seg = (uint32_t*)p;
   p += align256(4 * g.nb);
-  w.worklist = (uint32_t*)p;
-  p += align256(4 * g.nb);
+  w.work = (uint4*)p;
+  p += align256(16 * g.nb);
   w.tile_sums = (uint32_t*)p;
   p += align256(4 * (g.tiles + 1));
   w.wl_len = (uint32_t*)p;
@@ -401,7 +426,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
                          int32_t* ids, const InsertWs& w, hipStream_t s) {
   const Geo g = geometry(c, n_rows);
   hipError_t e;
-  if ((e = launch_fill_u32(w.wl_len, 1, 0u, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(w.wl_len, 2, 0u, s)) != hipSuccess) return e;
   if (n_rows <= 0) return launch_fill_u32(counts, g.nb, 0u, s);
   // table-major keys
   hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
@@ -435,14 +460,15 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.seg = w.seg;
   a.staged = w.staged;
   a.ids = ids;
-  a.worklist = w.worklist;
+  a.work = w.work;
   a.wl_len = w.wl_len;
   a.n_buckets = g.nb;
   a.s_p = c.seeds.s_p;
   a.M = c.M;
   a.R = c.R;
-  hipLaunchKernelGGL(bucket_select_small_kernel, dim3(grid_for(g.nb, 256, 16)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bucket_select_wave_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_mid_kernel, dim3(device_info().cus * 16), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

@@ -74,6 +74,10 @@ def lib():
                              ctypes.c_size_t, _VP],
         "flash_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP,
                               _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_query_keys_mixed": [P, _VP, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP,
+                                   _VP, ctypes.c_size_t, _VP],
+        "flash_query_batch_mixed": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.c_int32,
+                                    _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
                             ctypes.c_size_t, _VP],
     }
@@ -202,6 +206,33 @@ def flash_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_id
                                    q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx), _p(self_ids),
                                    k, _p(out_ids), _p(out_counts), _p(workspace),
                                    workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_query_keys_mixed(p, counts, ids, n_indexed, qkeys, k_per_query, k_max, out_ids,
+                           out_counts, workspace, self_ids=None, stream=None):
+    q = qkeys.numel() // p.L
+    _need(k_per_query, q, (torch.int32,), "k_per_query")
+    _need(out_ids, q * k_max, (torch.int32,), "out_ids")
+    _need(out_counts, q * k_max, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    _check(lib().flash_query_keys_mixed(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q, _p(qkeys),
+                                        _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
+                                        _p(out_counts), _p(workspace),
+                                        workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_query_batch_mixed(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
+                            out_ids, out_counts, workspace, self_ids=None, stream=None):
+    q = q_row_ptr.numel() - 1
+    _need(k_per_query, q, (torch.int32,), "k_per_query")
+    _need(out_ids, q * k_max, (torch.int32,), "out_ids")
+    _need(out_counts, q * k_max, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    _check(lib().flash_query_batch_mixed(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+                                         q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
+                                         _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
+                                         _p(out_counts), _p(workspace),
+                                         workspace.numel() * workspace.element_size(), _s(stream)))
 
 
 def flash_knn_graph(p, row_ptr, col_idx, k, counts, ids, out_ids, out_counts, workspace,

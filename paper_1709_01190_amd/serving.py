@@ -1,0 +1,261 @@
+"""Serving loop for the FLASH query path: continuous batching over a resident index.
+
+The index (counts, ids) stays in HBM.  Requests are CSR batches of query rows
+with their own k.  Two servers share one interface:
+
+* ContinuousServer: a request is admitted as soon as it has arrived, a slot
+  (one HIP stream) is free and its device memory fits the HBM budget; each
+  admitted request runs flash_query_batch on its own stream, so requests that
+  arrive while others are on the GPU start at once and overlap on the device.
+  Completion is polled with events; latency = completion seen - arrival.
+* BatchAllServer: the plain baseline.  While one batch runs, arrivals wait;
+  when it ends, everything that has arrived (within the budget) is
+  concatenated into one batch, queried with the largest k of the batch, and
+  each request takes the prefix of its own k.  The top-k by (count desc, id
+  asc) is a prefix of the top-k' for k' >= k, so both servers return the same
+  lists, and recall is equal by construction.
+
+A request larger than the whole budget is rejected (it never runs).  All
+arithmetic is in the HIP library; this module moves buffers and schedules.
+The device side sits behind a small executor interface so that the
+scheduling logic can be exercised without a GPU.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import time
+from typing import Callable, Dict, List, Optional, Sequence
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float                # seconds after the start of the run
+    row_ptr: np.ndarray           # int64 [n + 1]
+    col_idx: np.ndarray           # int32 [nnz]
+    k: int
+    out_ids: Optional[np.ndarray] = None
+    out_counts: Optional[np.ndarray] = None
+    admitted: float = math.nan
+    done: float = math.nan
+    rejected: bool = False
+
+    @property
+    def n(self) -> int:
+        return int(self.row_ptr.shape[0] - 1)
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col_idx.shape[0])
+
+    @property
+    def latency(self) -> float:
+        return self.done - self.arrival
+
+
+def make_requests(row_source: Callable[[int, int], tuple], n_requests: int, qps: float, seed: int,
+                  max_batch: int = 4096, ks: Sequence[int] = (10, 50, 200)) -> List[Request]:
+    """Poisson request arrivals carrying `qps` queries per second on average;
+    batch sizes log-uniform on [1, max_batch]; k uniform over ks.
+    row_source(n, seed) returns (row_ptr, col_idx) numpy arrays for n rows."""
+    rng = np.random.default_rng(seed)
+    sizes = np.floor(np.exp(rng.uniform(0.0, math.log(max_batch + 1), size=n_requests))).astype(np.int64)
+    sizes = np.clip(sizes, 1, max_batch)
+    rate = qps / float(sizes.mean())                   # requests per second
+    gaps = rng.exponential(1.0 / rate, size=n_requests)
+    arrivals = np.cumsum(gaps) - gaps[0]
+    kk = rng.choice(np.asarray(ks), size=n_requests)
+    return [Request(i, float(arrivals[i]), *row_source(int(sizes[i]), int(seed) * 1_000_003 + i),
+                    int(kk[i])) for i in range(n_requests)]
+
+
+# ---------------------------------------------------------------- executors
+
+class GpuExecutor:
+    """Runs requests through the C ABI on per-slot HIP streams."""
+
+    def __init__(self, p, counts, ids, n_indexed, device="cuda"):
+        import torch
+        from . import flash
+        self._torch, self._flash = torch, flash
+        self.p, self.counts, self.ids, self.n_indexed = p, counts, ids, n_indexed
+        self.device = torch.device(device)
+
+    def bytes_for(self, n: int, nnz: int, k: int) -> int:
+        """Device memory one request holds while in flight."""
+        ws = self._flash.flash_workspace_bytes(self._flash.OP_QUERY, self.p, n_queries=n, k=k)
+        return 8 * (n + 1) + 4 * nnz + ws + 8 * n * k
+
+    def new_slot(self):
+        torch = self._torch
+        return {"stream": torch.cuda.Stream(device=self.device), "event": torch.cuda.Event(),
+                "bufs": None}
+
+    def launch(self, slot, row_ptr: np.ndarray, col_idx: np.ndarray, k: int) -> None:
+        torch, flash = self._torch, self._flash
+        n = row_ptr.shape[0] - 1
+        s = slot["stream"]
+        with torch.cuda.stream(s):
+            rp_h = torch.from_numpy(row_ptr).pin_memory()
+            ci_h = torch.from_numpy(col_idx).pin_memory()
+            rp_d = rp_h.to(self.device, non_blocking=True)
+            ci_d = ci_h.to(self.device, non_blocking=True)
+            oi = torch.empty(max(n * k, 1), dtype=torch.int32, device=self.device)
+            oc = torch.empty(max(n * k, 1), dtype=torch.int32, device=self.device)
+            ws = flash.alloc_workspace(flash.OP_QUERY, self.p, n_queries=n, k=k, device=self.device)
+            if n > 0:
+                flash.flash_query_batch(self.p, self.counts, self.ids, self.n_indexed, rp_d, ci_d, k,
+                                        oi, oc, ws, stream=s)
+            oi_h = torch.empty(oi.shape, dtype=torch.int32, pin_memory=True)
+            oc_h = torch.empty(oc.shape, dtype=torch.int32, pin_memory=True)
+            oi_h.copy_(oi, non_blocking=True)
+            oc_h.copy_(oc, non_blocking=True)
+            slot["event"].record(s)
+        # every buffer stays referenced until the stream has passed it
+        slot["bufs"] = (rp_h, ci_h, rp_d, ci_d, oi, oc, ws, oi_h, oc_h)
+
+    def done(self, slot) -> bool:
+        return bool(slot["event"].query())
+
+    def result(self, slot, n: int, k: int):
+        oi_h, oc_h = slot["bufs"][-2], slot["bufs"][-1]
+        out = (oi_h.numpy()[: n * k].reshape(n, k).copy(), oc_h.numpy()[: n * k].reshape(n, k).copy())
+        slot["bufs"] = None
+        return out
+
+
+# ---------------------------------------------------------------- servers
+
+class ContinuousServer:
+    """Continuous batching: admit by arrival, a free slot and the HBM budget."""
+
+    def __init__(self, executor, budget_bytes: int = 4 << 30, slots: int = 8):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.slots = [executor.new_slot() for _ in range(slots)]
+
+    def run(self, requests: List[Request], clock=time.perf_counter) -> Dict:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        free = list(range(len(self.slots)))
+        busy: Dict[int, tuple] = {}
+        in_use = 0
+        t0 = clock()
+        while pending or busy:
+            now = clock() - t0
+            progressed = False
+            for si in list(busy):
+                if self.ex.done(self.slots[si]):
+                    seen = clock() - t0
+                    r, nbytes = busy.pop(si)
+                    r.out_ids, r.out_counts = self.ex.result(self.slots[si], r.n, r.k)
+                    r.done = seen
+                    in_use -= nbytes
+                    free.append(si)
+                    progressed = True
+            now = clock() - t0
+            while pending and pending[0].arrival <= now and free:
+                r = pending[0]
+                need = self.ex.bytes_for(r.n, r.nnz, r.k)
+                if need > self.budget:
+                    pending.popleft()
+                    r.rejected = True
+                    progressed = True
+                    continue
+                if in_use + need > self.budget:
+                    break                                  # wait until memory frees up
+                pending.popleft()
+                si = free.pop()
+                in_use += need
+                r.admitted = now
+                self.ex.launch(self.slots[si], r.row_ptr, r.col_idx, r.k)
+                busy[si] = (r, need)
+                progressed = True
+            if not progressed and not busy and pending:
+                wait = pending[0].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        return summarize(requests)
+
+
+class BatchAllServer:
+    """Baseline: one batch at a time; everything that has arrived goes in."""
+
+    def __init__(self, executor, budget_bytes: int = 4 << 30):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.slot = executor.new_slot()
+
+    def run(self, requests: List[Request], clock=time.perf_counter) -> Dict:
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        t0 = clock()
+        running: List[Request] = []
+        kmax = 0
+        while pending or running:
+            now = clock() - t0
+            if running:
+                if self.ex.done(self.slot):
+                    done = clock() - t0
+                    total = sum(r.n for r in running)
+                    oi, oc = self.ex.result(self.slot, total, kmax)
+                    off = 0
+                    for r in running:
+                        r.out_ids = oi[off:off + r.n, : r.k].copy()
+                        r.out_counts = oc[off:off + r.n, : r.k].copy()
+                        r.done = done
+                        off += r.n
+                    running = []
+                continue
+            if pending and pending[0].arrival <= now:
+                batch: List[Request] = []
+                while pending and pending[0].arrival <= now:
+                    r = pending[0]
+                    if self.ex.bytes_for(r.n, r.nnz, r.k) > self.budget:
+                        pending.popleft()
+                        r.rejected = True
+                        continue
+                    k2 = max([x.k for x in batch] + [r.k])
+                    n2 = sum(x.n for x in batch) + r.n
+                    z2 = sum(x.nnz for x in batch) + r.nnz
+                    if batch and self.ex.bytes_for(n2, z2, k2) > self.budget:
+                        break
+                    pending.popleft()
+                    batch.append(r)
+                if not batch:
+                    continue
+                kmax = max(r.k for r in batch)
+                rps, base = [np.zeros(1, np.int64)], 0
+                for r in batch:
+                    rps.append(r.row_ptr[1:] + base)
+                    base += int(r.row_ptr[-1])
+                rp = np.concatenate(rps)
+                ci = np.concatenate([r.col_idx for r in batch])
+                for r in batch:
+                    r.admitted = now
+                self.ex.launch(self.slot, rp, ci, kmax)
+                running = batch
+                continue
+            if pending:
+                wait = pending[0].arrival - (clock() - t0)
+                if wait > 0:
+                    time.sleep(min(wait, 1e-3))
+        return summarize(requests)
+
+
+def summarize(requests: List[Request]) -> Dict:
+    ok = [r for r in requests if not r.rejected]
+    lat = np.array([r.latency for r in ok], dtype=np.float64)
+    queries = sum(r.n for r in ok)
+    span = max((r.done for r in ok), default=0.0) - min((r.arrival for r in ok), default=0.0)
+    return {
+        "requests": len(ok),
+        "rejected": len(requests) - len(ok),
+        "queries": int(queries),
+        "p50_ms": float(np.percentile(lat, 50) * 1e3) if lat.size else math.nan,
+        "p99_ms": float(np.percentile(lat, 99) * 1e3) if lat.size else math.nan,
+        "mean_ms": float(lat.mean() * 1e3) if lat.size else math.nan,
+        "qps": float(queries / span) if span > 0 else math.nan,
+    }

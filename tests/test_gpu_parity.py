@@ -418,3 +418,30 @@ def test_webspam_full_size_graph(fl, orc):
     gi = i32(oi)[sample]
     gc = i32(oc)[sample]
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+def test_query_mixed_k(fl, orc, tiny_index):
+    # one launch, a k per query: each row equals the fixed-k answer for its k,
+    # padded past it
+    import torch
+    say("query mixed k")
+    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    rng = np.random.default_rng(12)
+    q = 2500
+    qk = keys[rng.integers(0, keys.shape[0], size=q)]
+    kq = rng.choice([1, 10, 37, 100], size=q).astype(np.int32)
+    kq[7] = 0        # clamped to 1
+    kq[8] = 500      # clamped to k_max
+    k_max = 100
+    oi = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
+    oc = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
+    ws = fl.alloc_workspace(fl.OP_QUERY_KEYS, p, n_queries=q, k=k_max)
+    fl.flash_query_keys_mixed(p, counts, ids, keys.shape[0], dev(qk.astype(np.uint32), torch.int32),
+                              dev(kq), k_max, oi, oc, ws)
+    torch.cuda.synchronize()
+    gi, gc = i32(oi).reshape(q, k_max), i32(oc).reshape(q, k_max)
+    wi, wc = orc.query(op, ocounts, oids, qk, k_max)
+    for j in range(q):
+        kk = min(max(int(kq[j]), 1), k_max)
+        assert np.array_equal(gi[j, :kk], wi[j, :kk]) and np.array_equal(gc[j, :kk], wc[j, :kk])
+        assert np.all(gi[j, kk:] == -1) and np.all(gc[j, kk:] == 0)
