@@ -44,7 +44,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving"])
+    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving", "uneven"])
+    ap.add_argument("--queries", type=int, default=1_000_000, help="uneven: queries in the batch")
     ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
                     help="serving: offered queries per second, comma separated")
     ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
@@ -63,11 +64,11 @@ def main():
     if args.copy_mib:
         copy_calibration(args.copy_mib)
         return
-    if args.workload == "serving":
+    if args.workload in ("serving", "uneven"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
             sys.exit(2)
-        serving_bench(args)
+        (serving_bench if args.workload == "serving" else uneven_bench)(args)
         return
 
     if args.gpus != 1:
@@ -213,9 +214,11 @@ def serving_bench(args):
     torch.cuda.synchronize()
     del ws
     log(f"url-shaped index: {spec.n_rows} rows, {int(ci.numel())} nnz, built in {time.time() - t0:.1f}s")
-    # a pool of query rows (seed 2); each request takes a random slice of it
+    # a pool of query rows from the index's clusters (rows drawn with seed 2);
+    # each request takes a random slice of it
+    import dataclasses
     pool_n = 400_000
-    qrp_d, qci_d = datagen.make_rows(datagen.scaled(spec, pool_n), 2, device="cuda")
+    qrp_d, qci_d = datagen.make_rows(dataclasses.replace(spec, n_rows=pool_n), 1, device="cuda", row_seed=2)
     qrp, qci = qrp_d.cpu().numpy(), qci_d.cpu().numpy()
     del qrp_d, qci_d
 
@@ -278,6 +281,154 @@ def serving_bench(args):
                    "requests_per_rate": args.requests, "hbm_budget_bytes": budget, "slots": 8},
         "rates": table,
         "recall": recall,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def uneven_bench(args):
+    """Batched uneven queries against a resident 40M-row click-log-shaped index
+    (K=4, L=32, b=4, R=256): 1M queries whose sizes are Pareto,
+    clip(floor(5 U^-1), 5, 50000), drawn from the index's clusters, with k in
+    {10, 100} by a fair coin.  One persistent flash_query_batch_mixed launch
+    sequence (autotuned on the first 128K queries) against one
+    flash_query_batch call per (power-of-two size class, k) bucket; the
+    buckets' CSR gathers happen before the timed region."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import datagen, flash
+
+    torch.cuda.set_device(0)
+    spec = datagen.CLICKLOG
+    if args.rows:
+        spec = datagen.scaled(spec, args.rows)
+    K, L, b, R = 4, 32, 4, 256
+    t0 = time.time()
+    rp, ci = datagen.make_rows(spec, 1, device="cuda")
+    torch.cuda.synchronize()
+    log(f"click-log-shaped index rows: {spec.n_rows} rows, {int(ci.numel())} nnz in {time.time() - t0:.1f}s")
+    p = flash.flash_params.make(K, L, b, R, seed=1)
+    counts, ids = flash.alloc_index(p)
+    ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
+    stream = torch.cuda.current_stream()
+    build_ms = []
+    for _ in range(3):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        flash.flash_build_index(p, rp, ci, counts, ids, ws, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        build_ms.append(e0.elapsed_time(e1))
+    del ws
+    log(f"index build (hash + insert of {spec.n_rows} rows): {build_ms} ms")
+
+    nq = args.queries
+    sizes = datagen.heavy_tail_sizes(nq, 5, 50_000, 1.0, seed=2, device="cuda")
+    qrp, qci = datagen.make_rows(dataclasses.replace(spec, n_rows=nq), 1, device="cuda", row_seed=2,
+                                 sizes=sizes)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(2)
+    kq_h = torch.where(torch.rand(nq, generator=g) < 0.5, 10, 100).to(torch.int32)
+    kq = kq_h.cuda()
+    lens = (qrp[1:] - qrp[:-1])
+    torch.cuda.synchronize()
+    log(f"queries: {nq}, {int(qci.numel())} nnz, median {int(lens.median())}, max {int(lens.max())}")
+    kmax = 100
+    oi = torch.empty(nq * kmax, dtype=torch.int32, device="cuda")
+    oc = torch.empty_like(oi)
+    qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=nq, k=kmax)
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return out
+
+    def persistent():
+        flash.flash_query_batch_mixed(p, counts, ids, spec.n_rows, qrp, qci, kq, kmax, oi, oc, qws,
+                                      stream=stream)
+
+    flash.flash_set_tuning(None)
+    timed(persistent, args.warmup)
+    default_ms = timed(persistent, args.steps)
+    # autotune on the first 128K queries
+    ns = min(nq, 131072)
+    srp, sci = qrp[:ns + 1], qci[: int(qrp[ns])]
+    soi = torch.empty(ns * kmax, dtype=torch.int32, device="cuda")
+    soc = torch.empty_like(soi)
+    sws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=ns, k=kmax)
+    best, best_ms = flash.flash_autotune_query_batch(p, counts, ids, spec.n_rows, srp, sci, kq[:ns].contiguous(),
+                                                     kmax, soi, soc, sws, reps=2, stream=stream)
+    log(f"autotuned on {ns} queries: {best.as_dict()} ({best_ms:.3f} ms)")
+    timed(persistent, args.warmup)
+    tuned_ms = timed(persistent, args.steps)
+    torch.cuda.synchronize()
+
+    # baseline: one launch per (size class, k) bucket, default tuning
+    flash.flash_set_tuning(None)
+    cls = torch.ceil(torch.log2(lens.double())).to(torch.int64)
+    bucket_key = (cls * 1000 + kq.to(torch.int64)).cpu().numpy()
+    buckets = []
+    for key in np.unique(bucket_key):
+        sel = torch.from_numpy(np.nonzero(bucket_key == key)[0]).cuda()
+        blen = lens[sel]
+        brp = torch.zeros(sel.numel() + 1, dtype=torch.int64, device="cuda")
+        brp[1:] = torch.cumsum(blen, 0)
+        starts = torch.repeat_interleave(qrp[:-1][sel] - brp[:-1], blen)
+        bci = qci[starts + torch.arange(int(brp[-1]), device="cuda")]
+        bk = int(key % 1000)
+        boi = torch.empty(sel.numel() * bk, dtype=torch.int32, device="cuda")
+        boc = torch.empty_like(boi)
+        bws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=sel.numel(), k=bk)
+        buckets.append((sel, brp, bci, bk, boi, boc, bws))
+    log(f"per-bucket baseline: {len(buckets)} (size class, k) buckets")
+
+    def per_bucket():
+        for sel, brp, bci, bk, boi, boc, bws in buckets:
+            flash.flash_query_batch(p, counts, ids, spec.n_rows, brp, bci, bk, boi, boc, bws, stream=stream)
+
+    timed(per_bucket, args.warmup)
+    bucket_ms = timed(per_bucket, args.steps)
+    # identical lists: scatter the buckets back into query order
+    got_i = torch.full((nq, kmax), -1, dtype=torch.int32, device="cuda")
+    got_c = torch.zeros((nq, kmax), dtype=torch.int32, device="cuda")
+    for sel, brp, bci, bk, boi, boc, bws in buckets:
+        got_i[sel, :bk] = boi.view(-1, bk)
+        got_c[sel, :bk] = boc.view(-1, bk)
+    same = bool(torch.equal(got_i.view(-1), oi) and torch.equal(got_c.view(-1), oc))
+    med = lambda v: float(np.median(v))
+    t_p, t_b = med(tuned_ms), med(bucket_ms)
+    out = {
+        "metric": "uneven batch queries per second (40M-row click-log-shape index)",
+        "value": round(nq / (t_p / 1e3), 1),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_p, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "click-log-shaped uneven batch", "index_rows": spec.n_rows,
+                   "index_nnz": int(ci.numel()), "queries": nq, "query_nnz": int(qci.numel()),
+                   "K": K, "L": L, "bits_per_hash": b, "R": R, "k": [10, 100]},
+        "persistent_autotuned_ms": round(t_p, 3),
+        "persistent_default_ms": round(med(default_ms), 3),
+        "per_bucket_ms": round(t_b, 3),
+        "per_bucket_launches": len(buckets),
+        "speedup_vs_per_bucket": round(t_b / t_p, 3),
+        "tuning": best.as_dict(),
+        "index_build_ms": round(med(build_ms), 3),
+        "identical_lists": same,
     }
     print(json.dumps(out), flush=True)
 

@@ -176,6 +176,51 @@ FLASH_API int flash_knn_graph(const flash_params *p, int64_t n_rows, int64_t nnz
                               int32_t *out_counts, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+/* Launch shapes (process-wide).  No field changes any result: they only
+ * move the same work between launches, workgroups and waves.  A value of
+ * 0 in a field marked "0 = ..." has that meaning; reserved must be 0. */
+typedef struct flash_tuning {
+    int32_t query_cap1;          /* LDS table entries of the first query stage (queries with at
+                                    most 3/4 of it in candidates); 0 = no such stage, else
+                                    1024..16384, rounded down to a power of two.  Default 2048 */
+    int32_t query_cap2;          /* the same for the second stage; default 4096 */
+    int32_t query_blocks_per_cu; /* one-wave workgroups per CU in the first stage, 1..1024;
+                                    default 128 */
+    int32_t query_big_waves;     /* waves per workgroup that share one query in the last stage
+                                    when its table has >= 8192 entries: 1, 4, 8 or 16; default 8 */
+    int32_t hash_tile_rows;      /* flash_query_batch*: 0 = static row stride; else each wave
+                                    takes tiles of this many rows from a work counter,
+                                    1..65536; default 0 */
+    int32_t reserved[3];
+} flash_tuning;
+
+/* Current tuning (host struct). */
+FLASH_API int flash_get_tuning(flash_tuning *out);
+
+/* Replaces the tuning (host struct; NULL restores the defaults).  Values are
+ * checked as documented above (FLASH_EINVAL).  Launches already enqueued
+ * keep the shape they were enqueued with. */
+FLASH_API int flash_set_tuning(const flash_tuning *t);
+
+/* Autotuner for a batch of (uneven) CSR queries: runs the batch as
+ * flash_query_batch_mixed (k_per_query may be NULL: k_max for all) under a
+ * fixed list of candidate tunings, one field at a time (coordinate descent),
+ * timing each run with HIP events on `stream`, keeps the fastest (the least
+ * of `reps` runs, 1..20), installs it with flash_set_tuning and copies it to
+ * *best (host) and its time to *best_ms (host, may be NULL).  Unlike every
+ * other entry point it blocks: it synchronises `stream` after each run.
+ * The outputs hold the batch's result (the same for every candidate).
+ * Arguments as flash_query_batch_mixed; workspace FLASH_OP_QUERY.  On error
+ * the previous tuning is restored. */
+FLASH_API int flash_autotune_query_batch(const flash_params *p, const uint32_t *counts,
+                                         const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+                                         int64_t nnz, const int64_t *q_row_ptr,
+                                         const int32_t *q_col_idx, const int32_t *self_ids,
+                                         const int32_t *k_per_query, int32_t k_max,
+                                         int32_t *out_ids, int32_t *out_counts, void *workspace,
+                                         size_t workspace_bytes, int32_t reps, void *stream,
+                                         flash_tuning *best, float *best_ms);
+
 /* Text for a FLASH_* code (static storage). */
 FLASH_API const char *flash_strerror(int code);
 

@@ -185,6 +185,31 @@ __device__ __forceinline__ void rank_write(const uint32_t* scratch, uint32_t m, 
   }
 }
 
+// Output length of query q: its own k clamped to [1, kmax], else kmax.
+__device__ __forceinline__ uint32_t query_k(const QueryArgs& a, uint64_t q, uint32_t kmax) {
+  if (!a.k_per_query) return kmax;
+  const int32_t kk = a.k_per_query[q];
+  return kk < 1 ? 1u : ((uint32_t)kk > kmax ? kmax : (uint32_t)kk);
+}
+
+// Appends the n pending hand-on queries (lane i holds the i-th) to the
+// overflow list with one atomic; returns 0.
+__device__ __forceinline__ uint32_t flush_overflow(const QueryArgs& a, uint32_t buf, uint32_t n) {
+  const uint32_t lane = threadIdx.x & 63;
+  uint32_t pos = 0;
+  if (lane == 0) pos = atomicAdd(a.ovf_len, n);
+  pos = rl(pos, 0);
+  if (lane < n) a.ovf_list[pos + lane] = buf;
+  return 0;
+}
+
+// Orders this wave's earlier LDS accesses before its later ones, for data
+// that lanes of the same wave exchange through LDS.
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <int CAP, int LCH, bool ALIGNED>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
@@ -208,15 +233,12 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   for (uint32_t i = lane; i < (uint32_t)W; i += kWave) scratch[i] = kEmpty;
   __syncthreads();
 
+  uint32_t ovf_buf = 0, ovf_n = 0;  // pending hand-ons: lane i holds the i-th
   const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
   for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
     const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
-    uint32_t k = kmax;
-    if (a.k_per_query) {
-      const int32_t kk = a.k_per_query[q];
-      k = kk < 1 ? 1u : ((uint32_t)kk > kmax ? kmax : (uint32_t)kk);
-    }
+    const uint32_t k = query_k(a, q, kmax);
 
     // 1. occupancy of the L buckets.  Each bucket's occupied slots are cut
     // into tasks of 4 consecutive slots (one 16-byte load); one packed scan
@@ -253,7 +275,9 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     }
     const uint32_t total = carry >> 16, n_tasks = carry & 0xFFFFu;
     if (total > a.max_total) {
-      if (lane == 0) a.ovf_list[atomicAdd(a.ovf_len, 1u)] = (uint32_t)q;
+      // hand the query on; appends are batched 64 at a time (one atomic each)
+      if (lane == ovf_n) ovf_buf = (uint32_t)q;
+      if (++ovf_n == (uint32_t)kWave) ovf_n = flush_overflow(a, ovf_buf, ovf_n);
       continue;
     }
     for (uint32_t c = lane; c <= L; c += kWave) hist[c] = 0;
@@ -452,6 +476,291 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     // leave the window marks empty for the next query
     for (uint32_t i = lane; i < (uint32_t)W; i += kWave) scratch[i] = kEmpty;
   }
+  if (ovf_n) flush_overflow(a, ovf_buf, ovf_n);
+}
+
+// LDS bytes of the workgroup kernel: table, per-wave window marks (reused for
+// the survivors), table info, histogram and 8 control words.
+__host__ __device__ inline uint32_t block_scratch(uint32_t sb, int nw) {
+  return sb > (uint32_t)(nw * 256) ? sb : (uint32_t)(nw * 256);
+}
+__host__ __device__ inline size_t block_smem_bytes(int cap, int L, uint32_t sb, int nw) {
+  return (size_t)cap * 4 + (size_t)block_scratch(sb, nw) * 4 + (size_t)L * 16 + (size_t)(L + 1) * 4 + 32;
+}
+
+// The same query steps for queries with many candidates, by a workgroup of
+// NW wavefronts that share one LDS table, so that a CU keeps 8-16 waves in
+// flight although the table takes 32-64 KB.  Waves take the gather windows in
+// turn; the table is swept in place (no compaction) with the sweeps split
+// over all threads; block-wide sums go through LDS words.  Wave 0 sorts and
+// writes the survivors.
+template <int CAP, int LCH, bool ALIGNED, int NW>
+__global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) {
+  constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
+  constexpr int W = kWave * U;         // tasks per window
+  constexpr uint32_t NT = kWave * NW;  // threads
+  constexpr int kLog = __builtin_ctz(CAP);
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t scr_n = block_scratch(a.sb, NW);
+  uint32_t* tab = (uint32_t*)smem;                                    // [CAP]
+  uint32_t* scratch = tab + CAP;                                      // [scr_n]
+  uint4* tinfo = reinterpret_cast<uint4*>(scratch + scr_n);           // [L]
+  uint32_t* hist = reinterpret_cast<uint32_t*>(tinfo + a.L);          // [L + 1]
+  uint32_t* ctrl = hist + a.L + 1;  // [0] distinct ids, [1..3] bisection counts, [4] survivors
+
+  const uint32_t tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  uint32_t* marks = scratch + wv * W;                                 // this wave's window marks
+  const uint32_t L = (uint32_t)a.L;
+  const uint32_t R = (uint32_t)a.R;
+  const uint32_t cb = (uint32_t)a.cbits;
+  const uint32_t cmask = (1u << cb) - 1u;
+  const uint32_t kmax = (uint32_t)a.k;
+  const uint32_t idshift = 32u - cb;
+  uint4* tab4 = reinterpret_cast<uint4*>(tab);
+  for (uint32_t i = tid; i < (uint32_t)CAP / 4; i += NT) tab4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+  for (uint32_t i = tid; i < scr_n; i += NT) scratch[i] = kEmpty;
+  __syncthreads();
+
+  const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
+  for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
+    const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
+    const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
+    const uint32_t k = query_k(a, q, kmax);
+
+    // 1. occupancy (every wave keeps the per-table registers; wave 0 publishes tinfo)
+    uint32_t tstart[LCH], tcnt[LCH];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int c = 0; c < LCH; ++c) {
+      const uint32_t t = (uint32_t)c * 64 + lane;
+      uint32_t nt = 0;
+      uint64_t base = 0;
+      if (t < L) {
+        const uint32_t key = a.qkeys[q * (uint64_t)L + t];
+        if (key < a.M) {
+          const uint64_t bucket = (uint64_t)t * a.M + key;
+          const uint32_t cnt = a.counts[bucket];
+          nt = cnt < R ? cnt : R;
+          base = bucket * R;
+        }
+      }
+      const uint32_t ct = (nt + 3) >> 2;
+      const uint32_t packed = (nt << 16) | ct;
+      const uint32_t inc = wave_incl_scan(packed);
+      const uint32_t pre = carry + inc - packed;
+      tstart[c] = pre & 0xFFFFu;
+      tcnt[c] = ct;
+      if (wv == 0 && t < L)
+        tinfo[t] = make_uint4((uint32_t)(base - 4ull * tstart[c]), (uint32_t)((base - 4ull * tstart[c]) >> 32),
+                              4u * tstart[c] + nt, 0u);
+      carry += rl(inc, 63);
+    }
+    const uint32_t n_tasks = carry & 0xFFFFu;
+    if (wv == 0) {
+      for (uint32_t c = lane; c <= L; c += kWave) hist[c] = 0;
+      if (lane < 8) ctrl[lane] = 0;
+    }
+    __syncthreads();
+
+    // 2-3. gather and count; wave wv takes windows wv, wv + NW, ...
+    for (uint32_t base = wv * (uint32_t)W; base < n_tasks; base += NW * (uint32_t)W) {
+      uint32_t tf = 0;
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) {
+        const uint32_t t = (uint32_t)c * 64 + lane;
+        const bool ne = tcnt[c] > 0;
+        if (ne && tstart[c] > base && tstart[c] < base + W) marks[tstart[c] - base] = t;
+        const uint64_t bal = __ballot(ne && tstart[c] <= base);
+        if (bal) tf = (uint32_t)c * 64 + 63 - (uint32_t)__clzll((long long)bal);
+      }
+      if (lane == 0) marks[0] = tf;
+      wave_lds_sync();
+      uint32_t tcarry = 0;
+      uint4 ids4[U];
+      uint32_t vmask[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t mk = marks[u * kWave + lane];
+        marks[u * kWave + lane] = kEmpty;
+        uint32_t tt = wave_incl_max(mk == kEmpty ? 0u : mk + 1);
+        tt = tt > tcarry ? tt : tcarry;
+        tcarry = rl(tt, 63);
+        const uint32_t task = base + (uint32_t)u * kWave + lane;
+        const uint32_t tc = task < n_tasks ? task : n_tasks - 1;
+        const uint4 ti = tinfo[tt - 1];
+        const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
+        const uint32_t room = ti.z - 4u * tc;
+        vmask[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
+        if (ALIGNED) {
+          ids4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
+        } else {
+          const uint32_t last = room - 1;
+          ids4[u].x = (uint32_t)a.ids[addr];
+          ids4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
+          ids4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
+          ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t id[4] = {ids4[u].x, ids4[u].y, ids4[u].z, ids4[u].w};
+        bool pend[4];
+        uint32_t slot[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          pend[j] = ((vmask[u] >> j) & 1u) && (int64_t)id[j] != self;
+          slot[j] = (id[j] * 0x9E3779B1u) >> (32 - kLog);
+        }
+        while (pend[0] || pend[1] || pend[2] || pend[3]) {
+          uint32_t old[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            old[j] = pend[j] ? atomicCAS(&tab[slot[j]], kEmpty, (id[j] << cb) | 1u) : 0u;
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            if (!pend[j]) continue;
+            if (old[j] == kEmpty) {
+              pend[j] = false;
+            } else if ((old[j] >> cb) == id[j]) {
+              atomicAdd(&tab[slot[j]], 1u);
+              pend[j] = false;
+            } else {
+              slot[j] = (slot[j] + 1) & (CAP - 1);
+            }
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+    __syncthreads();
+
+    // 4. histogram of the counts over the whole table (count 1 in registers)
+    uint32_t ones = 0, nd = 0;
+    for (uint32_t i = tid; i < (uint32_t)CAP / 4; i += NT) {
+      const uint4 v4 = tab4[i];
+      const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (v[j] == kEmpty) continue;
+        ++nd;
+        const uint32_t c = v[j] & cmask;
+        if (c == 1) ++ones;
+        else atomicAdd(&hist[c], 1u);
+      }
+    }
+    ones = wave_sum(ones);
+    nd = wave_sum(nd);
+    if (lane == 0) {
+      if (ones) atomicAdd(&hist[1], ones);
+      atomicAdd(&ctrl[0], nd);
+    }
+    __syncthreads();
+    nd = ctrl[0];
+
+    // 5. c* (every wave computes the same value), then the id threshold for
+    // ties, bisected on block-wide counts (ctrl[1 + it % 3]: the word for the
+    // round after next is cleared while this one is summed)
+    uint32_t cstar = 0, thr = 0xFFFFFFFFu;
+    if (nd > k) {
+      uint32_t above = 0;
+      bool found = false;
+      for (int c0 = (int)L; c0 >= 1 && !found; c0 -= kWave) {
+        const int c = c0 - (int)lane;
+        const uint32_t h = c >= 1 ? hist[c] : 0u;
+        const uint32_t inc = wave_incl_scan(h);
+        const uint64_t hit = __ballot(above + inc >= k);
+        if (hit) {
+          const uint32_t f = (uint32_t)__ffsll((unsigned long long)hit) - 1;
+          cstar = (uint32_t)(c0 - (int)f);
+          above += rl(inc - h, f);
+          found = true;
+        } else {
+          above += rl(inc, 63);
+        }
+      }
+      const uint32_t need = k - above;
+      const uint32_t ties = hist[cstar];
+      const uint32_t slack = slack_for(need);
+      if (ties > need + slack) {
+        const uint64_t span = (uint64_t)a.n_indexed;
+        uint64_t lo = 0, hi = span;
+        uint64_t g = (uint64_t)((float)(need + slack / 2) * ((float)span / (float)ties)) + 1;
+        if (g >= hi) g = hi - 1;
+        if (g <= lo) g = lo + 1;
+        for (int it = 0; it < 64; ++it) {
+          uint32_t cnt = 0;
+          for (uint32_t i = tid; i < (uint32_t)CAP / 4; i += NT) {
+            const uint4 v4 = tab4[i];
+            cnt += ((v4.x & cmask) == cstar && (uint64_t)(v4.x >> cb) < g) +
+                   ((v4.y & cmask) == cstar && (uint64_t)(v4.y >> cb) < g) +
+                   ((v4.z & cmask) == cstar && (uint64_t)(v4.z >> cb) < g) +
+                   ((v4.w & cmask) == cstar && (uint64_t)(v4.w >> cb) < g);
+          }
+          cnt = wave_sum(cnt);
+          uint32_t* word = ctrl + 1 + it % 3;
+          if (lane == 0 && cnt) atomicAdd(word, cnt);
+          if (tid == 0) ctrl[1 + (it + 1) % 3] = 0;
+          __syncthreads();
+          cnt = *word;
+          if (cnt < need) {
+            lo = g;
+          } else if (cnt > need + slack) {
+            hi = g;
+          } else {
+            break;
+          }
+          g = (lo + hi) / 2;
+          if (g == lo) break;
+        }
+        thr = (uint32_t)g;
+      }
+    }
+
+    // 6. survivors -> scratch[0, m) (the table is cleared on the way)
+    for (uint32_t i0 = wv * (uint32_t)kWave; i0 < (uint32_t)CAP; i0 += NT) {
+      const uint32_t i = i0 + lane;
+      const uint32_t v = tab[i];
+      bool sel = false;
+      uint32_t key = 0;
+      if (v != kEmpty) {
+        tab[i] = kEmpty;
+        const uint32_t c = v & cmask, idv = v >> cb;
+        sel = c > cstar || (c == cstar && idv < thr);
+        key = ((L - c) << idshift) | idv;
+      }
+      const uint64_t mk = __ballot(sel);
+      if (mk) {
+        uint32_t pos0 = 0;
+        if (lane == 0) pos0 = atomicAdd(&ctrl[4], (uint32_t)__popcll(mk));
+        const uint32_t pos = rl(pos0, 0) + mbcnt(mk);
+        if (sel && pos < a.sb) scratch[pos] = key;
+      }
+    }
+    __syncthreads();
+
+    // 7. wave 0 sorts and writes, then restores the marks it overwrote
+    if (wv == 0) {
+      uint32_t m = ctrl[4];
+      if (m > a.sb) m = a.sb;
+      const uint64_t orow = q * (uint64_t)kmax;
+      for (uint32_t j = k + lane; j < kmax; j += kWave) {
+        a.out_ids[orow + j] = -1;
+        a.out_counts[orow + j] = 0;
+      }
+      const uint32_t idmask = (idshift >= 32) ? 0xFFFFFFFFu : ((1u << idshift) - 1u);
+      if (m <= 64) {
+        sort_write<1>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else if (m <= 128) {
+        sort_write<2>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else if (m <= 256) {
+        sort_write<4>(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else {
+        rank_write(scratch, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      }
+      wave_lds_sync();
+      for (uint32_t i = lane; i < m; i += kWave) scratch[i] = kEmpty;
+    }
+  }
 }
 
 template <int CAP, int LCH, bool ALIGNED>
@@ -495,9 +804,60 @@ hipError_t launch_any(int cap, const QueryArgs& a, int grid, hipStream_t st) {
   }
 }
 
-int env_int(const char* name, int dflt) {
-  const char* v = getenv(name);
-  return v && *v ? atoi(v) : dflt;
+template <int CAP, int LCH, bool ALIGNED, int NW>
+hipError_t launch_block_kernel(const QueryArgs& a, int grid, hipStream_t st) {
+  const size_t lds = block_smem_bytes(CAP, a.L, a.sb, NW);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    const hipError_t e = hipFuncSetAttribute(
+        reinterpret_cast<const void*>(&count_topk_block_kernel<CAP, LCH, ALIGNED, NW>),
+        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((count_topk_block_kernel<CAP, LCH, ALIGNED, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
+  return hipGetLastError();
+}
+
+template <int CAP, int LCH, int NW>
+hipError_t launch_block_aligned(const QueryArgs& a, int grid, hipStream_t st) {
+  return a.r_aligned ? launch_block_kernel<CAP, LCH, true, NW>(a, grid, st)
+                     : launch_block_kernel<CAP, LCH, false, NW>(a, grid, st);
+}
+
+template <int LCH, int NW>
+hipError_t launch_block_cap(int cap, const QueryArgs& a, int grid, hipStream_t st) {
+  switch (cap) {
+    case 8192: return launch_block_aligned<8192, LCH, NW>(a, grid, st);
+    case 16384: return launch_block_aligned<16384, LCH, NW>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int NW>
+hipError_t launch_block_lch(int cap, const QueryArgs& a, int grid, hipStream_t st) {
+  switch ((a.L + 63) / 64) {
+    case 1: return launch_block_cap<1, NW>(cap, a, grid, st);
+    case 2: return launch_block_cap<2, NW>(cap, a, grid, st);
+    case 3: return launch_block_cap<3, NW>(cap, a, grid, st);
+    case 4: return launch_block_cap<4, NW>(cap, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_block_any(int nw, int cap, const QueryArgs& a, int grid, hipStream_t st) {
+  switch (nw) {
+    case 4: return launch_block_lch<4>(cap, a, grid, st);
+    case 8: return launch_block_lch<8>(cap, a, grid, st);
+    case 16: return launch_block_lch<16>(cap, a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Supported table size at or below v (powers of two, 1024 .. 16384).
+int supported_cap(int v) {
+  int c = 1024;
+  while (c < 16384 && 2 * c <= v) c <<= 1;
+  return c;
 }
 
 }  // namespace
@@ -544,24 +904,22 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   const uint32_t full = (uint32_t)c.L * (uint32_t)c.R;  // most candidates a query can have
   uint32_t last = 1024;
   while (last < 2 * full) last <<= 1;                   // table that takes any query at load 1/2
+  const Tuning tu = tuning();
   int caps[3];
   int n_stage = 0;
-  // first and second table sizes (tuning knobs), rounded to a supported power of two
-  auto supported = [](int v) {
-    int c = 1024;
-    while (c < 16384 && 2 * c <= v) c <<= 1;
-    return c;
-  };
-  const int c0 = supported(env_int("FLASH_QUERY_CAP", 2048));
-  const int c1 = supported(env_int("FLASH_QUERY_CAP2", 4096));
-  for (int cap : {c0, c1}) {
+  // first and second table sizes (0: no such stage), rounded to a supported size
+  for (int v : {tu.query_cap1, tu.query_cap2}) {
+    if (v <= 0) continue;
+    const int cap = supported_cap(v);
     if ((uint32_t)cap >= last) break;
     if (n_stage == 0 || cap > caps[n_stage - 1]) caps[n_stage++] = cap;
   }
   caps[n_stage++] = (int)last;
+  // the last stage runs as one workgroup of NW waves per query when its table is large
+  const int nw = (last >= 8192 && tu.query_big_waves > 1) ? tu.query_big_waves : 1;
 
   const int cus = device_info().cus;
-  const int per_cu = env_int("FLASH_QUERY_BLOCKS_PER_CU", 128);
+  const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 128;
   hipError_t e;
   if (n_stage > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
   for (int s = 0; s < n_stage; ++s) {
@@ -578,6 +936,17 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     if (!final_stage) {
       b.ovf_list = w.ovf_list[s & 1];
       b.ovf_len = w.ovf_len + (s & 1);
+    }
+    if (final_stage && nw > 1) {
+      // as many workgroups as fit on the CUs at once (LDS and 32 waves per CU)
+      const size_t lds = block_smem_bytes(caps[s], c.L, b.sb, nw);
+      int per = (int)((160 * 1024) / lds);
+      if (per > 32 / nw) per = 32 / nw;
+      if (per < 1) per = 1;
+      const int64_t want = (int64_t)cus * per;
+      const int grid = (int)(n_queries < want ? n_queries : want);
+      if ((e = launch_block_any(nw, caps[s], b, grid, st)) != hipSuccess) return e;
+      continue;
     }
     int64_t want = (int64_t)cus * per_cu;
     if (s > 0) want = (int64_t)cus * 8;

@@ -33,6 +33,8 @@ struct HashArgs {
   int B, K, L, b, A;
   uint32_t mask;
   int shift;  // 32 - log2(B) when B is a power of two
+  uint32_t* tile_ctr;  // dynamic schedule's work counter (null: static)
+  int64_t tile_rows;
 };
 
 template <bool POW2>
@@ -50,18 +52,15 @@ __device__ __forceinline__ bool occupied(const uint32_t* occw, uint32_t j) {
   return (occw[j >> 5] >> (j & 31)) & 1u;
 }
 
+// Hashes one row with the whole wave; mins/occw/top_bin are the wave's LDS.
 template <bool POW2>
-__global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
-  extern __shared__ uint32_t lds[];
-  uint32_t* mins = lds;              // [B]
-  uint32_t* occw = lds + a.B;        // [ceil(B / 32)]
-  __shared__ uint32_t top_bin;
+__device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_t* mins, uint32_t* occw,
+                                         uint32_t& top_bin) {
   const int lane = threadIdx.x;
   const int B = a.B;
   const int nwords = (B + 31) >> 5;
   const uintptr_t mis = ((uintptr_t)a.col_idx >> 2) & 3;  // element misalignment vs 16 B
-
-  for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) {
+  {
     int64_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
     beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
     end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
@@ -75,7 +74,7 @@ __global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
       if (a.codes)
         for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = kEmpty;
       __syncthreads();
-      continue;
+      return;
     }
 
     // 1. bin minima.  a0/a1: first/last 16-byte aligned element positions.
@@ -165,11 +164,35 @@ __global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
   }
 }
 
+// Static schedule: wave w hashes rows w, w + grid, ...  Dynamic schedule
+// (for batches of very uneven rows): each wave takes tiles of tile_rows
+// consecutive rows from a work counter until the tiles run out.
+template <bool POW2>
+__global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
+  extern __shared__ uint32_t lds[];
+  uint32_t* mins = lds;              // [B]
+  uint32_t* occw = lds + a.B;        // [ceil(B / 32)]
+  __shared__ uint32_t top_bin;
+  if (a.tile_ctr) {
+    for (;;) {
+      uint32_t t = 0;
+      if (threadIdx.x == 0) t = atomicAdd(a.tile_ctr, 1u);
+      t = (uint32_t)__builtin_amdgcn_readlane((int)t, 0);
+      const int64_t r0 = (int64_t)t * a.tile_rows;
+      if (r0 >= a.n_rows) break;
+      const int64_t r1 = r0 + a.tile_rows < a.n_rows ? r0 + a.tile_rows : a.n_rows;
+      for (int64_t row = r0; row < r1; ++row) hash_row<POW2>(a, row, mins, occw, top_bin);
+    }
+  } else {
+    for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) hash_row<POW2>(a, row, mins, occw, top_bin);
+  }
+}
+
 }  // namespace
 
 hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
                             const int32_t* col_idx, uint32_t* keys, uint32_t* codes,
-                            hipStream_t s) {
+                            uint32_t* tile_ctr, hipStream_t s) {
   if (n_rows <= 0) return hipSuccess;
   HashArgs a;
   a.row_ptr = row_ptr;
@@ -191,6 +214,13 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
   const size_t lds = sizeof(uint32_t) * ((size_t)c.B + (size_t)((c.B + 31) / 32));
   const int64_t want = (int64_t)device_info().cus * 32;
   const int grid = (int)(n_rows < want ? n_rows : want);
+  const int tile = tuning().hash_tile_rows;
+  a.tile_ctr = tile > 0 ? tile_ctr : nullptr;
+  a.tile_rows = tile > 0 ? tile : 1;
+  if (a.tile_ctr) {
+    const hipError_t e = launch_fill_u32(a.tile_ctr, 1, 0u, s);
+    if (e != hipSuccess) return e;
+  }
   if (pow2)
     hipLaunchKernelGGL(doph_hash_kernel<true>, dim3(grid), dim3(64), lds, s, a);
   else

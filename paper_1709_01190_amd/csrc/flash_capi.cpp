@@ -96,9 +96,59 @@ const Device& device_info() {
   return infos[dev];
 }
 
+std::mutex g_tuning_mu;
+Tuning g_tuning;
+
+Tuning tuning() {
+  std::lock_guard<std::mutex> lock(g_tuning_mu);
+  return g_tuning;
+}
+
 }  // namespace flashk
 
 using namespace flashk;
+
+namespace {
+
+int tuning_from_c(const flash_tuning* t, Tuning* out) {
+  if (!t) {
+    *out = Tuning();
+    return FLASH_OK;
+  }
+  if (t->reserved[0] || t->reserved[1] || t->reserved[2])
+    return fail(FLASH_EINVAL, "tuning.reserved must be 0");
+  for (int v : {t->query_cap1, t->query_cap2})
+    if (v != 0 && (v < 1024 || v > 16384)) return fail(FLASH_EINVAL, "query caps must be 0 or in [1024, 16384]");
+  if (t->query_blocks_per_cu < 1 || t->query_blocks_per_cu > 1024)
+    return fail(FLASH_EINVAL, "query_blocks_per_cu must be in [1, 1024]");
+  const int w = t->query_big_waves;
+  if (w != 1 && w != 4 && w != 8 && w != 16) return fail(FLASH_EINVAL, "query_big_waves must be 1, 4, 8 or 16");
+  if (t->hash_tile_rows < 0 || t->hash_tile_rows > 65536)
+    return fail(FLASH_EINVAL, "hash_tile_rows must be in [0, 65536]");
+  out->query_cap1 = t->query_cap1;
+  out->query_cap2 = t->query_cap2;
+  out->query_blocks_per_cu = t->query_blocks_per_cu;
+  out->query_big_waves = t->query_big_waves;
+  out->hash_tile_rows = t->hash_tile_rows;
+  return FLASH_OK;
+}
+
+flash_tuning tuning_to_c(const Tuning& t) {
+  flash_tuning o = {};
+  o.query_cap1 = t.query_cap1;
+  o.query_cap2 = t.query_cap2;
+  o.query_blocks_per_cu = t.query_blocks_per_cu;
+  o.query_big_waves = t.query_big_waves;
+  o.hash_tile_rows = t.hash_tile_rows;
+  return o;
+}
+
+void install_tuning(const Tuning& t) {
+  std::lock_guard<std::mutex> lock(g_tuning_mu);
+  g_tuning = t;
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -150,7 +200,7 @@ FLASH_API int flash_hash(const flash_params* p, int64_t n_rows, int64_t nnz, con
   if ((r = check_rows(c, n_rows, false))) return r;
   if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
   if (n_rows > 0 && !keys) return fail(FLASH_EINVAL, "keys is NULL");
-  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, codes, (hipStream_t)stream);
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, codes, nullptr, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "doph_hash");
 }
 
@@ -186,7 +236,7 @@ FLASH_API int flash_build_index(const flash_params* p, int64_t n_rows, int64_t n
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_BUILD)");
   uint32_t* keys = keys_out ? keys_out : (uint32_t*)workspace;
   hipStream_t s = (hipStream_t)stream;
-  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, s);
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   const InsertWs w = insert_ws_carve(c, n_rows, (char*)workspace + kb);
   e = launch_insert(c, n_rows, keys, counts, ids, w, s);
@@ -232,9 +282,10 @@ FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, c
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY)");
   hipStream_t s = (hipStream_t)stream;
   uint32_t* qkeys = (uint32_t*)workspace;
-  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  // the query workspace's spare word 2 counts the hash tiles (dynamic schedule)
   const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
+  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
   e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k,
                    nullptr, out_ids, out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
@@ -279,9 +330,10 @@ FLASH_API int flash_query_batch_mixed(const flash_params* p, const uint32_t* cou
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY)");
   hipStream_t s = (hipStream_t)stream;
   uint32_t* qkeys = (uint32_t*)workspace;
-  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, s);
-  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  // the query workspace's spare word 2 counts the hash tiles (dynamic schedule)
   const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
+  hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
   e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k_max,
                    k_per_query, out_ids, out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
@@ -307,13 +359,110 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   hipStream_t s = (hipStream_t)stream;
   uint32_t* keys = (uint32_t*)workspace;
   char* rest = (char*)workspace + kb;
-  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, s);
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   e = launch_insert(c, n_rows, keys, counts, ids, insert_ws_carve(c, n_rows, rest), s);
   if (e != hipSuccess) return hip_fail(e, "reservoir_insert");
   e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, nullptr, out_ids, out_counts,
                    query_ws_carve(c, n_rows, rest), s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
+FLASH_API int flash_get_tuning(flash_tuning* out) {
+  if (!out) return fail(FLASH_EINVAL, "out is NULL");
+  *out = tuning_to_c(tuning());
+  return FLASH_OK;
+}
+
+FLASH_API int flash_set_tuning(const flash_tuning* t) {
+  Tuning v;
+  const int r = tuning_from_c(t, &v);
+  if (r) return r;
+  install_tuning(v);
+  return FLASH_OK;
+}
+
+FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                                         int64_t n_indexed, int64_t n_queries, int64_t nnz,
+                                         const int64_t* q_row_ptr, const int32_t* q_col_idx,
+                                         const int32_t* self_ids, const int32_t* k_per_query,
+                                         int32_t k_max, int32_t* out_ids, int32_t* out_counts,
+                                         void* workspace, size_t workspace_bytes, int32_t reps,
+                                         void* stream, flash_tuning* best, float* best_ms) {
+  if (reps < 1 || reps > 20) return fail(FLASH_EINVAL, "reps must be in [1, 20]");
+  if (!best) return fail(FLASH_EINVAL, "best is NULL");
+  const Tuning before = tuning();
+  hipStream_t s = (hipStream_t)stream;
+  auto run_once = [&]() {
+    return k_per_query
+               ? flash_query_batch_mixed(p, counts, ids, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx,
+                                         self_ids, k_per_query, k_max, out_ids, out_counts, workspace,
+                                         workspace_bytes, stream)
+               : flash_query_batch(p, counts, ids, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx, self_ids,
+                                   k_max, out_ids, out_counts, workspace, workspace_bytes, stream);
+  };
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    if (e0) (void)hipEventDestroy(e0);
+    return fail(FLASH_EHIP, "hipEventCreate failed");
+  }
+  int rc = FLASH_OK;
+  // time of one candidate: the least of reps runs (ms), or a negative code
+  auto measure = [&](const Tuning& t, float* ms) -> int {
+    install_tuning(t);
+    float bestt = 3.4e38f;
+    for (int i = 0; i < reps; ++i) {
+      hipError_t he = hipEventRecord(e0, s);
+      if (he != hipSuccess) return hip_fail(he, "hipEventRecord");
+      const int r = run_once();
+      if (r) return r;
+      if ((he = hipEventRecord(e1, s)) != hipSuccess) return hip_fail(he, "hipEventRecord");
+      if ((he = hipEventSynchronize(e1)) != hipSuccess) return hip_fail(he, "hipEventSynchronize");
+      float v = 0.f;
+      if ((he = hipEventElapsedTime(&v, e0, e1)) != hipSuccess) return hip_fail(he, "hipEventElapsedTime");
+      if (v < bestt) bestt = v;
+    }
+    *ms = bestt;
+    return FLASH_OK;
+  };
+  Tuning cur = before;
+  float cur_ms = 0.f;
+  rc = measure(cur, &cur_ms);  // also warms up
+  if (!rc) rc = measure(cur, &cur_ms);
+  // candidate values, one field at a time
+  const int waves[] = {1, 4, 8, 16};
+  const int stages[][2] = {{2048, 4096}, {2048, 0}, {1024, 4096}, {4096, 0}, {1024, 0}, {0, 0}};
+  const int per_cu[] = {32, 64, 128, 256};
+  const int tiles[] = {0, 4, 16, 64};
+  for (int field = 0; field < 4 && !rc; ++field) {
+    const int n = field == 1 ? 6 : 4;
+    for (int i = 0; i < n && !rc; ++i) {
+      Tuning t = cur;
+      if (field == 0) t.query_big_waves = waves[i];
+      if (field == 1) {
+        t.query_cap1 = stages[i][0];
+        t.query_cap2 = stages[i][1];
+      }
+      if (field == 2) t.query_blocks_per_cu = per_cu[i];
+      if (field == 3) t.hash_tile_rows = tiles[i];
+      float ms = 0.f;
+      rc = measure(t, &ms);
+      if (!rc && ms < cur_ms) {
+        cur = t;
+        cur_ms = ms;
+      }
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) {
+    install_tuning(before);
+    return rc;
+  }
+  install_tuning(cur);
+  *best = tuning_to_c(cur);
+  if (best_ms) *best_ms = cur_ms;
+  return FLASH_OK;
 }
 
 FLASH_API const char* flash_strerror(int code) {

@@ -21,10 +21,21 @@ struct Device {
 };
 const Device& device_info();
 
+// Launch-shape choices; none of them changes any result.  Process-wide.
+struct Tuning {
+  int query_cap1 = 2048;          // first query stage's table entries (0: no such stage)
+  int query_cap2 = 4096;          // second stage's (0: none)
+  int query_blocks_per_cu = 128;  // first-stage blocks per CU
+  int query_big_waves = 8;        // waves per workgroup in a last stage of >= 8192 entries (1: one wave)
+  int hash_tile_rows = 0;         // 0: static row stride; else rows per tile taken from a work counter
+};
+Tuning tuning();
+
 // ---- hash (doph_hash.hip)
+// tile_ctr: a device word for the dynamic schedule (may be null: static stride)
 hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
                             const int32_t* col_idx, uint32_t* keys, uint32_t* codes,
-                            hipStream_t s);
+                            uint32_t* tile_ctr, hipStream_t s);
 
 // ---- insert (reservoir_insert.hip)
 struct InsertWs {

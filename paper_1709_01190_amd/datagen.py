@@ -50,13 +50,16 @@ class RowSpec:
 
 def _chunk_rows(spec: RowSpec, row0: int, nr: int, cores: torch.Tensor,
                 perm: torch.Tensor, g: torch.Generator,
-                device) -> Tuple[torch.Tensor, torch.Tensor]:
+                device, sizes: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor]:
     """Rows [row0, row0 + nr): returns (nnz per row int64, sorted cols int64)."""
     core = cores.shape[1]
-    hi = spec.hi if spec.hi is not None else spec.n_cols
-    mu = math.log(spec.mean_nnz) - 0.5 * spec.sigma * spec.sigma
-    z = torch.randn(nr, generator=g, device=device, dtype=torch.float64)
-    n = torch.exp(mu + spec.sigma * z).round().clamp_(spec.lo, min(hi, spec.n_cols)).to(torch.int64)
+    if sizes is None:
+        hi = spec.hi if spec.hi is not None else spec.n_cols
+        mu = math.log(spec.mean_nnz) - 0.5 * spec.sigma * spec.sigma
+        z = torch.randn(nr, generator=g, device=device, dtype=torch.float64)
+        n = torch.exp(mu + spec.sigma * z).round().clamp_(spec.lo, min(hi, spec.n_cols)).to(torch.int64)
+    else:
+        n = sizes.to(device=device, dtype=torch.int64).clamp(1, spec.n_cols)
     clus = torch.randint(0, cores.shape[0], (nr,), generator=g, device=device)
 
     # core part: Bernoulli(keep) mask over the cluster core, first n kept
@@ -108,9 +111,16 @@ def _chunk_rows(spec: RowSpec, row0: int, nr: int, cores: torch.Tensor,
     return cnt, col
 
 
-def make_rows(spec: RowSpec, seed: int, device="cpu",
-              chunk_rows: int = 65536) -> Tuple[torch.Tensor, torch.Tensor]:
-    """Returns (row_ptr int64 [n_rows + 1], col_idx int32 [nnz]) on ``device``."""
+def make_rows(spec: RowSpec, seed: int, device="cpu", chunk_rows: int = 65536,
+              row_seed: Optional[int] = None,
+              sizes: Optional[torch.Tensor] = None) -> Tuple[torch.Tensor, torch.Tensor]:
+    """Returns (row_ptr int64 [n_rows + 1], col_idx int32 [nnz]) on ``device``.
+
+    ``seed`` draws the clusters and the noise permutation.  With ``row_seed``
+    the rows themselves are drawn from a generator of that seed, so rows of
+    another draw (queries) come from the same clusters as the rows of
+    ``seed`` alone (the indexed set).  ``sizes`` (int64 [n_rows]) replaces
+    the lognormal target sizes."""
     device = torch.device(device)
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
@@ -118,10 +128,16 @@ def make_rows(spec: RowSpec, seed: int, device="cpu",
     cores = torch.randint(0, spec.n_cols, (max(1, spec.n_clusters), core),
                           generator=g, device=device)
     perm = torch.randperm(spec.n_cols, generator=g, device=device)
+    if row_seed is not None:
+        g = torch.Generator(device=device)
+        g.manual_seed(int(row_seed))
+    if sizes is not None and sizes.numel() != spec.n_rows:
+        raise ValueError("sizes must have n_rows entries")
     counts, cols = [], []
     for r0 in range(0, spec.n_rows, chunk_rows):
         nr = min(chunk_rows, spec.n_rows - r0)
-        c, col = _chunk_rows(spec, r0, nr, cores, perm, g, device)
+        c, col = _chunk_rows(spec, r0, nr, cores, perm, g, device,
+                             None if sizes is None else sizes[r0:r0 + nr])
         counts.append(c)
         cols.append(col.to(torch.int32))
     cnt = torch.cat(counts) if counts else torch.zeros(0, dtype=torch.int64, device=device)

@@ -47,6 +47,15 @@ class flash_params(ctypes.Structure):
         return 1 << (self.K * self.bits_per_hash)
 
 
+class flash_tuning(ctypes.Structure):
+    _fields_ = [("query_cap1", ctypes.c_int32), ("query_cap2", ctypes.c_int32),
+                ("query_blocks_per_cu", ctypes.c_int32), ("query_big_waves", ctypes.c_int32),
+                ("hash_tile_rows", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+
+    def as_dict(self) -> dict:
+        return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}
+
+
 _lib = None
 _VP = ctypes.c_void_p
 _I64 = ctypes.c_int64
@@ -80,6 +89,12 @@ def lib():
                                     _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
                             ctypes.c_size_t, _VP],
+        "flash_get_tuning": [ctypes.POINTER(flash_tuning)],
+        "flash_set_tuning": [ctypes.POINTER(flash_tuning)],
+        "flash_autotune_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP,
+                                       ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t,
+                                       ctypes.c_int32, _VP, ctypes.POINTER(flash_tuning),
+                                       ctypes.POINTER(ctypes.c_float)],
     }
     for name, args in sig.items():
         fn = getattr(L, name)
@@ -233,6 +248,39 @@ def flash_query_batch_mixed(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_p
                                          _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
                                          _p(out_counts), _p(workspace),
                                          workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_get_tuning() -> flash_tuning:
+    t = flash_tuning()
+    _check(lib().flash_get_tuning(ctypes.byref(t)))
+    return t
+
+
+def flash_set_tuning(t: Optional[flash_tuning] = None, **fields) -> None:
+    """Installs `t` (None: the defaults); keyword fields modify the current tuning."""
+    if fields:
+        t = flash_get_tuning() if t is None else t
+        for k, v in fields.items():
+            setattr(t, k, int(v))
+    _check(lib().flash_set_tuning(ctypes.byref(t) if t is not None else None))
+
+
+def flash_autotune_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
+                               out_ids, out_counts, workspace, self_ids=None, reps=3, stream=None):
+    """Returns (best flash_tuning, its time in ms); the best is installed."""
+    q = q_row_ptr.numel() - 1
+    _need(k_per_query, q, (torch.int32,), "k_per_query")
+    _need(out_ids, q * k_max, (torch.int32,), "out_ids")
+    _need(out_counts, q * k_max, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    best, ms = flash_tuning(), ctypes.c_float(0.0)
+    _check(lib().flash_autotune_query_batch(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+                                            q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
+                                            _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
+                                            _p(out_counts), _p(workspace),
+                                            workspace.numel() * workspace.element_size(), reps,
+                                            _s(stream), ctypes.byref(best), ctypes.byref(ms)))
+    return best, float(ms.value)
 
 
 def flash_knn_graph(p, row_ptr, col_idx, k, counts, ids, out_ids, out_counts, workspace,

@@ -268,7 +268,21 @@ def test_query_mixed_keys_and_self(fl, orc, tiny_index):
         assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
-def test_query_overflow_table(fl, orc, monkeypatch):
+@pytest.fixture
+def tuned(fl):
+    """Lets a test change the launch tuning; restores the defaults after it."""
+    fl.flash_set_tuning(None)
+    yield fl.flash_set_tuning
+    fl.flash_set_tuning(None)
+
+
+# launch shapes of the query stages: first/second table sizes (0: no such
+# stage) and the waves per workgroup of a large last stage
+STAGE_SHAPES = [dict(query_cap1=c1, query_cap2=c2, query_big_waves=w)
+                for (c1, c2) in ((1024, 4096), (2048, 0), (0, 0), (16384, 0)) for w in (1, 4, 8, 16)]
+
+
+def test_query_overflow_table(fl, orc, tuned):
     # buckets far fuller than the first-pass table: every query takes the
     # large-table launch; a second run with a table that fits checks both
     say("query overflow")
@@ -285,10 +299,11 @@ def test_query_overflow_table(fl, orc, monkeypatch):
     qk = keys[:700].copy()
     qk[100:400, 4:] = EMPTY     # small queries stay in the first pass
     wi, wc = orc.query(op, ocounts, oids, qk, 300, self_ids=np.arange(700, dtype=np.int32))
-    for cap in ("1024", "2048", "16384"):
-        monkeypatch.setenv("FLASH_QUERY_CAP", cap)
+    for shape in STAGE_SHAPES:
+        tuned(None)
+        tuned(**shape)
         oi, oc = gpu_query(fl, p, counts, ids, n, qk, 300, np.arange(700, dtype=np.int32))
-        assert np.array_equal(oi, wi) and np.array_equal(oc, wc), cap
+        assert np.array_equal(oi, wi) and np.array_equal(oc, wc), shape
 
 
 def test_query_many_tables(fl, orc):
@@ -307,13 +322,13 @@ def test_query_many_tables(fl, orc):
     assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
-def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, monkeypatch):
+def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, tuned):
     say("query launch shapes")
     p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
     n = keys.shape[0]
     ref = None
-    for per_cu in ("1", "4", "32"):
-        monkeypatch.setenv("FLASH_QUERY_BLOCKS_PER_CU", per_cu)
+    for per_cu in (1, 4, 32):
+        tuned(query_blocks_per_cu=per_cu)
         out = gpu_query(fl, p, counts, ids, n, keys, 16, np.arange(n, dtype=np.int32))
         if ref is None:
             ref = out
@@ -445,3 +460,131 @@ def test_query_mixed_k(fl, orc, tiny_index):
         kk = min(max(int(kq[j]), 1), k_max)
         assert np.array_equal(gi[j, :kk], wi[j, :kk]) and np.array_equal(gc[j, :kk], wc[j, :kk])
         assert np.all(gi[j, kk:] == -1) and np.all(gc[j, kk:] == 0)
+
+
+# ------------------------------------------------------------------ uneven batches
+
+def _uneven_queries(spec, n_queries, device="cuda"):
+    """Heavy-tailed query rows (Pareto sizes clip(floor(5 U^-1), 5, 50000))
+    from the clusters of `spec`'s rows (seed 1), drawn with seed 2, and a k
+    per query from {10, 100} by a fair seeded coin."""
+    import dataclasses
+    import torch
+    from paper_1709_01190_amd import datagen
+    sizes = datagen.heavy_tail_sizes(n_queries, 5, 50_000, 1.0, seed=2, device=device)
+    qrp, qci = datagen.make_rows(dataclasses.replace(spec, n_rows=n_queries), 1, device=device,
+                                 row_seed=2, sizes=sizes)
+    g = torch.Generator(device="cpu")
+    g.manual_seed(2)
+    kq = torch.where(torch.rand(n_queries, generator=g) < 0.5, 10, 100).to(torch.int32)
+    return qrp, qci, kq
+
+
+def _mixed_expected(orc, op, ocounts, oids, okeys_q, kq, k_max, self_ids=None):
+    """Row q: the first kq[q] entries of the k_max answer (the ranking is a
+    total order, so a shorter answer is its prefix), then (-1, 0)."""
+    wi, wc = orc.query(op, ocounts, oids, okeys_q, k_max, self_ids=self_ids)
+    wi, wc = wi.copy(), wc.copy()
+    for j, kk in enumerate(np.minimum(np.maximum(kq, 1), k_max)):
+        wi[j, kk:] = -1
+        wc[j, kk:] = 0
+    return wi, wc
+
+
+def _gpu_batch_mixed(fl, p, counts, ids, n_indexed, qrp_d, qci_d, kq, k_max):
+    import torch
+    q = qrp_d.numel() - 1
+    oi = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
+    oc = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
+    ws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=k_max)
+    fl.flash_query_batch_mixed(p, counts, ids, n_indexed, qrp_d, qci_d, dev(kq.numpy()), k_max, oi, oc, ws)
+    torch.cuda.synchronize()
+    return i32(oi).reshape(q, k_max), i32(oc).reshape(q, k_max)
+
+
+@pytest.fixture(scope="module")
+def saturated_index(fl, orc):
+    """Click-log-shaped rows (mean 11 nonzeros) with K=2, b=4: 256 buckets per
+    table, ~1,170 arrivals per bucket, so every reservoir of R=256 is full and
+    a query meets up to L*R = 8,192 candidates (the large last stage)."""
+    import dataclasses
+    import torch
+    from paper_1709_01190_amd import datagen
+    spec = dataclasses.replace(datagen.CLICKLOG, n_rows=300_000, n_clusters=3_000)
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    K, L, b, R = 2, 32, 4, 256
+    p = fl.flash_params.make(K, L, b, R, seed=1)
+    counts, ids = fl.alloc_index(p)
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
+    fl.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
+    torch.cuda.synchronize()
+    op = orc.params(K, L, b, R, seed=1)
+    okeys = orc.doph(op, rp_d.cpu().numpy(), ci_d.cpu().numpy())
+    ocounts, oids = orc.build_tables(op, okeys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
+    return spec, p, op, counts, ids, ocounts, oids
+
+
+def test_uneven_batch_every_launch_shape(fl, orc, saturated_index, tuned):
+    # heavy-tailed query sizes (5 .. 50,000 nonzeros) and mixed k in one
+    # batch, under every stage layout, workgroup width and hash schedule
+    spec, p, op, counts, ids, ocounts, oids = saturated_index
+    qrp_d, qci_d, kq = _uneven_queries(spec, 3000)
+    qrp, qci = qrp_d.cpu().numpy(), qci_d.cpu().numpy()
+    assert int((qrp[1:] - qrp[:-1]).max()) > 5000          # the tail is present
+    wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp, qci), kq.numpy(), 100)
+    for shape in STAGE_SHAPES + [dict(hash_tile_rows=t) for t in (1, 16, 4096)]:
+        say("uneven batch", shape)
+        tuned(None)
+        tuned(**shape)
+        gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+        assert np.array_equal(gi, wi) and np.array_equal(gc, wc), shape
+
+
+def test_autotune_query_batch(fl, orc, saturated_index, tuned):
+    import torch
+    say("autotune")
+    spec, p, op, counts, ids, ocounts, oids = saturated_index
+    qrp_d, qci_d, kq = _uneven_queries(spec, 2000)
+    q = 2000
+    oi = torch.empty(q * 100, dtype=torch.int32, device="cuda")
+    oc = torch.empty_like(oi)
+    ws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=100)
+    best, ms = fl.flash_autotune_query_batch(p, counts, ids, spec.n_rows, qrp_d, qci_d,
+                                             dev(kq.numpy()), 100, oi, oc, ws, reps=2)
+    torch.cuda.synchronize()
+    assert ms > 0 and fl.flash_get_tuning().as_dict() == best.as_dict()
+    wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp_d.cpu().numpy(), qci_d.cpu().numpy()),
+                             kq.numpy(), 100)
+    assert np.array_equal(i32(oi).reshape(q, 100), wi) and np.array_equal(i32(oc).reshape(q, 100), wc)
+    gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+def test_clicklog_full_size_uneven(fl, orc):
+    # The uneven-batch workload at full size: a 40M-row click-log-shaped
+    # index (K=4, L=32, b=4, R=256; most reservoirs full) compared in full
+    # with the oracle's, and 2,000 heavy-tailed queries with mixed k.
+    import torch
+    from paper_1709_01190_amd import datagen
+    say("click-log full size index + uneven queries")
+    spec = datagen.CLICKLOG
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    K, L, b, R = 4, 32, 4, 256
+    p = fl.flash_params.make(K, L, b, R, seed=1)
+    counts, ids = fl.alloc_index(p)
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
+    fl.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
+    torch.cuda.synchronize()
+    del ws
+    qrp_d, qci_d, kq = _uneven_queries(spec, 2000)
+    gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+    op = orc.params(K, L, b, R, seed=1)
+    okeys = orc.doph(op, rp_d.cpu().numpy(), ci_d.cpu().numpy())
+    del rp_d, ci_d
+    ocounts, oids = orc.build_tables(op, okeys)
+    del okeys
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
+    wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp_d.cpu().numpy(), qci_d.cpu().numpy()),
+                             kq.numpy(), 100)
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)

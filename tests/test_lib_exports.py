@@ -96,3 +96,25 @@ def test_binding_refuses_cpu_tensors(fl):
     keys = torch.zeros(2 * 16, dtype=torch.int32)
     with pytest.raises(ValueError):
         fl.flash_hash(p, rp, ci, keys)
+
+
+def test_tuning_is_checked_and_restorable(fl):
+    fl.flash_set_tuning(None)
+    d = fl.flash_get_tuning().as_dict()
+    assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 128,
+                 "query_big_waves": 8, "hash_tile_rows": 0}
+    fl.flash_set_tuning(query_big_waves=16, hash_tile_rows=32, query_cap2=0)
+    d2 = fl.flash_get_tuning().as_dict()
+    assert d2["query_big_waves"] == 16 and d2["hash_tile_rows"] == 32 and d2["query_cap2"] == 0
+    for bad in (dict(query_big_waves=3), dict(query_cap1=512), dict(query_cap2=32768),
+                dict(query_blocks_per_cu=0), dict(hash_tile_rows=-1)):
+        with pytest.raises(fl.FlashError) as e:
+            fl.flash_set_tuning(**bad)
+        assert e.value.code == fl.FLASH_EINVAL
+        assert fl.flash_get_tuning().as_dict() == d2       # a rejected tuning changes nothing
+    t = fl.flash_get_tuning()
+    t.reserved[1] = 7
+    with pytest.raises(fl.FlashError):
+        fl.flash_set_tuning(t)
+    fl.flash_set_tuning(None)
+    assert fl.flash_get_tuning().as_dict() == d
