@@ -479,6 +479,60 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   if (ovf_n) flush_overflow(a, ovf_buf, ovf_n);
 }
 
+// Adds 16 candidate ids per lane (bit j of `valid`: idv[j] takes part) to
+// the LDS table of CAP packed (id << cb | count) slots, with double hashing
+// (an odd stride per id, so a probe run visits every slot of the power-of-two
+// table; the table is at most half full).  All 16 first probes go out at
+// once; after that each lane retries one colliding id at a time, so every
+// retry instruction carries as many lanes as still have work.
+template <int CAP>
+__device__ __forceinline__ void count_ids16(uint32_t* tab, const uint32_t (&idv)[16], uint32_t valid,
+                                            uint32_t cb) {
+  constexpr int kLog = __builtin_ctz(CAP);
+  uint32_t old[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t slot = (idv[j] * 0x9E3779B1u) >> (32 - kLog);
+    old[j] = ((valid >> j) & 1u) ? atomicCAS(&tab[slot], kEmpty, (idv[j] << cb) | 1u) : kEmpty;
+  }
+  uint32_t pend = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (!((valid >> j) & 1u) || old[j] == kEmpty) continue;
+    if ((old[j] >> cb) == idv[j]) {
+      atomicAdd(&tab[(idv[j] * 0x9E3779B1u) >> (32 - kLog)], 1u);
+    } else {
+      pend |= 1u << j;
+    }
+  }
+  bool active = false;
+  uint32_t cid = 0, cslot = 0, cstep = 0;
+  for (;;) {
+    if (!active && pend) {
+      const uint32_t j = (uint32_t)__ffs(pend) - 1;
+      pend &= pend - 1;
+      cid = idv[0];
+#pragma unroll
+      for (int i = 1; i < 16; ++i) cid = j == (uint32_t)i ? idv[i] : cid;
+      cstep = ((cid * 0x85EBCA77u) >> (32 - kLog)) | 1u;
+      cslot = (((cid * 0x9E3779B1u) >> (32 - kLog)) + cstep) & (CAP - 1);
+      active = true;
+    }
+    if (!__any(active)) break;
+    if (active) {
+      const uint32_t o = atomicCAS(&tab[cslot], kEmpty, (cid << cb) | 1u);
+      if (o == kEmpty) {
+        active = false;
+      } else if ((o >> cb) == cid) {
+        atomicAdd(&tab[cslot], 1u);
+        active = false;
+      } else {
+        cslot = (cslot + cstep) & (CAP - 1);
+      }
+    }
+  }
+}
+
 // LDS bytes of the workgroup kernel: table, per-wave window marks (reused for
 // the survivors), table info, histogram and 8 control words.
 __host__ __device__ inline uint32_t block_scratch(uint32_t sb, int nw) {
@@ -601,35 +655,19 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
           ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
         }
       }
+      uint32_t idv[16];
+      uint32_t valid = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t id[4] = {ids4[u].x, ids4[u].y, ids4[u].z, ids4[u].w};
-        bool pend[4];
-        uint32_t slot[4];
+        idv[4 * u + 0] = ids4[u].x;
+        idv[4 * u + 1] = ids4[u].y;
+        idv[4 * u + 2] = ids4[u].z;
+        idv[4 * u + 3] = ids4[u].w;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          pend[j] = ((vmask[u] >> j) & 1u) && (int64_t)id[j] != self;
-          slot[j] = (id[j] * 0x9E3779B1u) >> (32 - kLog);
-        }
-        while (pend[0] || pend[1] || pend[2] || pend[3]) {
-          uint32_t old[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            old[j] = pend[j] ? atomicCAS(&tab[slot[j]], kEmpty, (id[j] << cb) | 1u) : 0u;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (!pend[j]) continue;
-            if (old[j] == kEmpty) {
-              pend[j] = false;
-            } else if ((old[j] >> cb) == id[j]) {
-              atomicAdd(&tab[slot[j]], 1u);
-              pend[j] = false;
-            } else {
-              slot[j] = (slot[j] + 1) & (CAP - 1);
-            }
-          }
-        }
+        for (int j = 0; j < 4; ++j)
+          if (((vmask[u] >> j) & 1u) && (int64_t)idv[4 * u + j] != self) valid |= 1u << (4 * u + j);
       }
+      count_ids16<CAP>(tab, idv, valid, cb);
       wave_lds_sync();
     }
     __syncthreads();
@@ -716,24 +754,32 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
       }
     }
 
-    // 6. survivors -> scratch[0, m) (the table is cleared on the way)
-    for (uint32_t i0 = wv * (uint32_t)kWave; i0 < (uint32_t)CAP; i0 += NT) {
-      const uint32_t i = i0 + lane;
-      const uint32_t v = tab[i];
-      bool sel = false;
-      uint32_t key = 0;
-      if (v != kEmpty) {
-        tab[i] = kEmpty;
-        const uint32_t c = v & cmask, idv = v >> cb;
-        sel = c > cstar || (c == cstar && idv < thr);
-        key = ((L - c) << idshift) | idv;
+    // 6. survivors -> scratch[0, m), four entries per lane (the table is
+    // cleared on the way)
+    for (uint32_t i = tid; i < (uint32_t)CAP / 4; i += NT) {
+      const uint4 v4 = tab4[i];
+      tab4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+      const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+      bool sel[4];
+      uint32_t n_sel = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t c = v[j] & cmask, idv = v[j] >> cb;
+        sel[j] = v[j] != kEmpty && (c > cstar || (c == cstar && idv < thr));
+        n_sel += sel[j];
       }
-      const uint64_t mk = __ballot(sel);
-      if (mk) {
+      const uint32_t inc = wave_incl_scan(n_sel);
+      const uint32_t tot = rl(inc, 63);
+      if (tot) {
         uint32_t pos0 = 0;
-        if (lane == 0) pos0 = atomicAdd(&ctrl[4], (uint32_t)__popcll(mk));
-        const uint32_t pos = rl(pos0, 0) + mbcnt(mk);
-        if (sel && pos < a.sb) scratch[pos] = key;
+        if (lane == 0) pos0 = atomicAdd(&ctrl[4], tot);
+        uint32_t pos = rl(pos0, 0) + inc - n_sel;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          if (!sel[j]) continue;
+          if (pos < a.sb) scratch[pos] = ((L - (v[j] & cmask)) << idshift) | (v[j] >> cb);
+          ++pos;
+        }
       }
     }
     __syncthreads();
