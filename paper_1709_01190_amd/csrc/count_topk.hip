@@ -210,6 +210,78 @@ __device__ __forceinline__ void wave_lds_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
+// Adds 16 candidate ids per lane (bit j of `valid`: idv[j] takes part) to
+// the LDS table of CAP packed (id << cb | count) slots, with double hashing
+// (an odd stride per id, so a probe run visits every slot of the power-of-two
+// table; the table is at most half full).  All 16 first probes go out at
+// once; after that each lane retries one colliding id at a time, so every
+// retry instruction carries as many lanes as still have work.
+template <int CAP>
+__device__ __forceinline__ void count_ids16(uint32_t* tab, const uint32_t (&idv)[16], uint32_t valid,
+                                            uint32_t cb) {
+  constexpr int kLog = __builtin_ctz(CAP);
+  uint32_t old[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const uint32_t slot = (idv[j] * 0x9E3779B1u) >> (32 - kLog);
+    old[j] = ((valid >> j) & 1u) ? atomicCAS(&tab[slot], kEmpty, (idv[j] << cb) | 1u) : kEmpty;
+  }
+  uint32_t pend = 0;
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    if (!((valid >> j) & 1u) || old[j] == kEmpty) continue;
+    if ((old[j] >> cb) == idv[j]) {
+      atomicAdd(&tab[(idv[j] * 0x9E3779B1u) >> (32 - kLog)], 1u);
+    } else {
+      pend |= 1u << j;
+    }
+  }
+  // P colliding ids per lane are retried at once
+  constexpr int P = 4;
+  bool act[P];
+  uint32_t cid[P], cslot[P], cstep[P];
+#pragma unroll
+  for (int r = 0; r < P; ++r) {
+    act[r] = false;
+    cid[r] = cslot[r] = cstep[r] = 0;
+  }
+  for (;;) {
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      if (!act[r] && pend) {
+        const uint32_t j = (uint32_t)__ffs(pend) - 1;
+        pend &= pend - 1;
+        uint32_t v = idv[0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i) v = j == (uint32_t)i ? idv[i] : v;
+        cid[r] = v;
+        cstep[r] = ((v * 0x85EBCA77u) >> (32 - kLog)) | 1u;
+        cslot[r] = (((v * 0x9E3779B1u) >> (32 - kLog)) + cstep[r]) & (CAP - 1);
+        act[r] = true;
+      }
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < P; ++r) any = any || act[r];
+    if (!__any(any)) break;
+    uint32_t o[P];
+#pragma unroll
+    for (int r = 0; r < P; ++r) o[r] = act[r] ? atomicCAS(&tab[cslot[r]], kEmpty, (cid[r] << cb) | 1u) : kEmpty;
+#pragma unroll
+    for (int r = 0; r < P; ++r) {
+      if (!act[r]) continue;
+      if (o[r] == kEmpty) {
+        act[r] = false;
+      } else if ((o[r] >> cb) == cid[r]) {
+        atomicAdd(&tab[cslot[r]], 1u);
+        act[r] = false;
+      } else {
+        cslot[r] = (cslot[r] + cstep[r]) & (CAP - 1);
+      }
+    }
+  }
+}
+
 template <int CAP, int LCH, bool ALIGNED>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
@@ -326,36 +398,19 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
           ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
         }
       }
+      uint32_t idv[16];
+      uint32_t valid = 0;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        const uint32_t id[4] = {ids4[u].x, ids4[u].y, ids4[u].z, ids4[u].w};
-        bool pend[4];
-        uint32_t slot[4];
+        idv[4 * u + 0] = ids4[u].x;
+        idv[4 * u + 1] = ids4[u].y;
+        idv[4 * u + 2] = ids4[u].z;
+        idv[4 * u + 3] = ids4[u].w;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          pend[j] = ((vmask[u] >> j) & 1u) && (int64_t)id[j] != self;
-          slot[j] = (id[j] * 0x9E3779B1u) >> (32 - kLog);
-        }
-        // linear probing (measured faster here than triangular probing)
-        while (pend[0] || pend[1] || pend[2] || pend[3]) {
-          uint32_t old[4];
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            old[j] = pend[j] ? atomicCAS(&tab[slot[j]], kEmpty, (id[j] << cb) | 1u) : 0u;
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            if (!pend[j]) continue;
-            if (old[j] == kEmpty) {
-              pend[j] = false;
-            } else if ((old[j] >> cb) == id[j]) {
-              atomicAdd(&tab[slot[j]], 1u);
-              pend[j] = false;
-            } else {
-              slot[j] = (slot[j] + 1) & (CAP - 1);
-            }
-          }
-        }
+        for (int j = 0; j < 4; ++j)
+          if (((vmask[u] >> j) & 1u) && (int64_t)idv[4 * u + j] != self) valid |= 1u << (4 * u + j);
       }
+      count_ids16<CAP>(tab, idv, valid, cb);
       __syncthreads();
     }
 
@@ -477,60 +532,6 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     for (uint32_t i = lane; i < (uint32_t)W; i += kWave) scratch[i] = kEmpty;
   }
   if (ovf_n) flush_overflow(a, ovf_buf, ovf_n);
-}
-
-// Adds 16 candidate ids per lane (bit j of `valid`: idv[j] takes part) to
-// the LDS table of CAP packed (id << cb | count) slots, with double hashing
-// (an odd stride per id, so a probe run visits every slot of the power-of-two
-// table; the table is at most half full).  All 16 first probes go out at
-// once; after that each lane retries one colliding id at a time, so every
-// retry instruction carries as many lanes as still have work.
-template <int CAP>
-__device__ __forceinline__ void count_ids16(uint32_t* tab, const uint32_t (&idv)[16], uint32_t valid,
-                                            uint32_t cb) {
-  constexpr int kLog = __builtin_ctz(CAP);
-  uint32_t old[16];
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    const uint32_t slot = (idv[j] * 0x9E3779B1u) >> (32 - kLog);
-    old[j] = ((valid >> j) & 1u) ? atomicCAS(&tab[slot], kEmpty, (idv[j] << cb) | 1u) : kEmpty;
-  }
-  uint32_t pend = 0;
-#pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    if (!((valid >> j) & 1u) || old[j] == kEmpty) continue;
-    if ((old[j] >> cb) == idv[j]) {
-      atomicAdd(&tab[(idv[j] * 0x9E3779B1u) >> (32 - kLog)], 1u);
-    } else {
-      pend |= 1u << j;
-    }
-  }
-  bool active = false;
-  uint32_t cid = 0, cslot = 0, cstep = 0;
-  for (;;) {
-    if (!active && pend) {
-      const uint32_t j = (uint32_t)__ffs(pend) - 1;
-      pend &= pend - 1;
-      cid = idv[0];
-#pragma unroll
-      for (int i = 1; i < 16; ++i) cid = j == (uint32_t)i ? idv[i] : cid;
-      cstep = ((cid * 0x85EBCA77u) >> (32 - kLog)) | 1u;
-      cslot = (((cid * 0x9E3779B1u) >> (32 - kLog)) + cstep) & (CAP - 1);
-      active = true;
-    }
-    if (!__any(active)) break;
-    if (active) {
-      const uint32_t o = atomicCAS(&tab[cslot], kEmpty, (cid << cb) | 1u);
-      if (o == kEmpty) {
-        active = false;
-      } else if ((o >> cb) == cid) {
-        atomicAdd(&tab[cslot], 1u);
-        active = false;
-      } else {
-        cslot = (cslot + cstep) & (CAP - 1);
-      }
-    }
-  }
 }
 
 // LDS bytes of the workgroup kernel: table, per-wave window marks (reused for
