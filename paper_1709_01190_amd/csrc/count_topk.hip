@@ -415,31 +415,34 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
     }
 
     // 4. compact the distinct entries to tab[0, nd) in place (each chunk is
-    // read and cleared before compacted entries are written into it), then
-    // histogram the counts: count 1 in registers, larger counts in LDS
-    uint32_t nd = 0;
+    // read and cleared before compacted entries are written into it) and
+    // histogram their counts on the way: count 1 in registers, larger counts
+    // in LDS.  Everything past nd is left empty.
+    uint32_t nd = 0, ones = 0;
     for (uint32_t i0 = 0; i0 < (uint32_t)CAP / 4; i0 += kWave) {
       const uint4 v4 = tab4[i0 + lane];
       tab4[i0 + lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
-      const uint32_t n4 = (v4.x != kEmpty) + (v4.y != kEmpty) + (v4.z != kEmpty) + (v4.w != kEmpty);
+      const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+      uint32_t n4 = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (v[j] == kEmpty) continue;
+        ++n4;
+        const uint32_t c = v[j] & cmask;
+        if (c == 1) ++ones;
+        else atomicAdd(&hist[c], 1u);
+      }
       const uint32_t inc = wave_incl_scan(n4);
       uint32_t pos = nd + inc - n4;
-      if (v4.x != kEmpty) tab[pos++] = v4.x;
-      if (v4.y != kEmpty) tab[pos++] = v4.y;
-      if (v4.z != kEmpty) tab[pos++] = v4.z;
-      if (v4.w != kEmpty) tab[pos++] = v4.w;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (v[j] != kEmpty) tab[pos++] = v[j];
       nd += rl(inc, 63);
     }
-    __syncthreads();
-    uint32_t ones = 0;
-    for (uint32_t i = lane; i < nd; i += kWave) {
-      const uint32_t c = tab[i] & cmask;
-      if (c == 1) ++ones;
-      else atomicAdd(&hist[c], 1u);
-    }
     ones = wave_sum(ones);
-    if (lane == 0) hist[1] = ones;
+    if (lane == 0) hist[1] += ones;
     __syncthreads();
+    const uint32_t nd4 = (nd + 3) / 4;  // sweeps read tab4[0, nd4); the tail is empty
 
     uint32_t cstar = 0, thr = 0xFFFFFFFFu;
     if (nd > k) {
@@ -472,10 +475,14 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
         if (g >= hi) g = hi - 1;
         if (g <= lo) g = lo + 1;
         for (int it = 0; it < 64; ++it) {
+          // empty slots never match: their count field is cmask > L >= c*
           uint32_t cnt = 0;
-          for (uint32_t i = lane; i < nd; i += kWave) {
-            const uint32_t v = tab[i];
-            cnt += (v & cmask) == cstar && (uint64_t)(v >> cb) < g;
+          for (uint32_t i = lane; i < nd4; i += kWave) {
+            const uint4 v4 = tab4[i];
+            cnt += ((v4.x & cmask) == cstar && (uint64_t)(v4.x >> cb) < g) +
+                   ((v4.y & cmask) == cstar && (uint64_t)(v4.y >> cb) < g) +
+                   ((v4.z & cmask) == cstar && (uint64_t)(v4.z >> cb) < g) +
+                   ((v4.w & cmask) == cstar && (uint64_t)(v4.w >> cb) < g);
           }
           cnt = wave_sum(cnt);
           if (cnt < need) {
@@ -492,23 +499,34 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
       }
     }
 
-    // 5. survivors -> scratch (tab[0, nd) is cleared on the way), sort, write
+    // 5. survivors -> scratch, four entries per lane (tab[0, nd) is cleared
+    // on the way), then sort and write
     uint32_t m = 0;
-    for (uint32_t i0 = 0; i0 < nd; i0 += kWave) {
+    for (uint32_t i0 = 0; i0 < nd4; i0 += kWave) {
       const uint32_t i = i0 + lane;
-      bool sel = false;
-      uint32_t key = 0;
-      if (i < nd) {
-        const uint32_t v = tab[i];
-        tab[i] = kEmpty;
-        const uint32_t c = v & cmask, idv = v >> cb;
-        sel = c > cstar || (c == cstar && idv < thr);
-        key = ((L - c) << idshift) | idv;
+      uint4 v4 = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+      if (i < nd4) {
+        v4 = tab4[i];
+        tab4[i] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
       }
-      const uint64_t mk = __ballot(sel);
-      const uint32_t pos = m + mbcnt(mk);
-      if (sel && pos < a.sb) scratch[pos] = key;
-      m += (uint32_t)__popcll(mk);
+      const uint32_t v[4] = {v4.x, v4.y, v4.z, v4.w};
+      bool sel[4];
+      uint32_t n_sel = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t c = v[j] & cmask, idv = v[j] >> cb;
+        sel[j] = v[j] != kEmpty && (c > cstar || (c == cstar && idv < thr));
+        n_sel += sel[j];
+      }
+      const uint32_t inc = wave_incl_scan(n_sel);
+      uint32_t pos = m + inc - n_sel;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        if (!sel[j]) continue;
+        if (pos < a.sb) scratch[pos] = ((L - (v[j] & cmask)) << idshift) | (v[j] >> cb);
+        ++pos;
+      }
+      m += rl(inc, 63);
     }
     if (m > a.sb) m = a.sb;
     __syncthreads();
