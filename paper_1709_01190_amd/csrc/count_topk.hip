@@ -236,8 +236,8 @@ __device__ __forceinline__ void count_ids16(uint32_t* tab, const uint32_t (&idv)
       pend |= 1u << j;
     }
   }
-  // P colliding ids per lane are retried at once
-  constexpr int P = 4;
+  // two colliding ids per lane are retried at once
+  constexpr int P = 2;
   bool act[P];
   uint32_t cid[P], cslot[P], cstep[P];
 #pragma unroll
