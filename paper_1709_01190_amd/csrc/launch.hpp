@@ -44,7 +44,7 @@ struct InsertWs {
   uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)
   uint32_t* partoff;    // [L * M * S]    exclusive prefix of part
   uint32_t* seg;        // [L * M]        first staged slot of each bucket
-  uint4* work;          // [L * M]        {bucket, start, size} for the wave-level selects
+  uint4* work;          // [L * M]        {bucket, start, size} of the large buckets
   uint32_t* tile_sums;  // [tiles + 1]    scan carries
   uint32_t* wl_len;     // [2]
 };

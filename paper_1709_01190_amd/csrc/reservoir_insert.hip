@@ -16,6 +16,8 @@
 //   select    : per bucket, the min(count, R) arrivals with the smallest
 //               priority, in ascending priority, into ids[t][m][0..)
 //               - buckets of <= 8 arrivals: one thread, ranks in registers
+//               - 9..64 arrivals: the wave of the bucket's thread, one arrival
+//                 per lane, a bitonic sort across the lanes in registers
 //               - larger buckets: one wave; all arrivals sorted in LDS when few,
 //                 else a priority threshold keeps ~2R candidates (bisected until
 //                 between R and the LDS capacity), which are then sorted.
@@ -205,7 +207,7 @@ struct SelectArgs {
   int32_t* ids;
   uint4* work;          // [nb] {bucket, first staged slot, arrivals, 0}: mid-size
                         // buckets from the front, large buckets from the back
-  uint32_t* wl_len;     // [2] mid-size and large bucket counts
+  uint32_t* wl_len;     // [2] [1]: large buckets listed ([0] unused)
   uint64_t n_buckets;
   uint64_t s_p;
   uint32_t M;
@@ -226,36 +228,6 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
   return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Thread per bucket.  Buckets with at most kSmall arrivals: rank each arrival
-// against the others in registers.  Larger buckets are listed for the
-// wave-level kernels, with their start and size so those need no lookup.
-__global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
-  const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = bk < a.n_buckets;
-  const uint32_t n = in ? a.counts[bk] : 0u;
-  const uint32_t start = in ? a.seg[bk] : 0u;
-  const bool mid = n > (uint32_t)kSmall && n <= kMid;
-  const bool big = n > kMid;
-  const uint32_t pm = wave_append(&a.wl_len[0], mid);
-  const uint32_t pb = wave_append(&a.wl_len[1], big);
-  if (mid) a.work[pm] = make_uint4((uint32_t)bk, start, n, 0u);
-  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, 0u);
-  if (n == 0 || n > (uint32_t)kSmall) return;
-  const uint32_t t = (uint32_t)(bk / a.M);
-  uint64_t pk[kSmall];
-#pragma unroll
-  for (int i = 0; i < kSmall; ++i)
-    pk[i] = (uint32_t)i < n ? priority(a.s_p, t, (uint32_t)a.staged[start + i]) : ~0ull;
-#pragma unroll
-  for (int i = 0; i < kSmall; ++i) {
-    if ((uint32_t)i >= n) break;
-    int r = 0;
-#pragma unroll
-    for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i];
-    if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
-  }
-}
-
 // Ascending sort of one 64-bit value per lane across the 64 lanes.
 __device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
   const uint32_t lane = threadIdx.x & 63;
@@ -271,20 +243,49 @@ __device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
   return v;
 }
 
-// One wave per mid-size bucket (kSmall < n <= 64): one arrival per lane,
-// bitonic sort across the wave in registers; no LDS, so occupancy is high.
-__global__ __launch_bounds__(256) void bucket_select_mid_kernel(SelectArgs a) {
+// Thread per bucket.  Buckets with at most kSmall arrivals: each thread ranks
+// its arrivals against each other in registers.  Buckets with kSmall < n <=
+// kMid: the wave takes them one after another, one arrival per lane, and
+// sorts across the lanes in registers.  Larger buckets are listed (with
+// their start and size) for the LDS kernel; they are rare, so their appends
+// are few.
+__global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint32_t len = a.wl_len[0];
+  const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = bk < a.n_buckets;
+  const uint32_t n = in ? a.counts[bk] : 0u;
+  const uint32_t start = in ? a.seg[bk] : 0u;
+  const bool big = n > kMid;
+  const uint32_t pb = wave_append(&a.wl_len[1], big);
+  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, 0u);
+  if (n >= 1 && n <= (uint32_t)kSmall) {
+    const uint32_t t = (uint32_t)(bk / a.M);
+    uint64_t pk[kSmall];
+#pragma unroll
+    for (int i = 0; i < kSmall; ++i)
+      pk[i] = (uint32_t)i < n ? priority(a.s_p, t, (uint32_t)a.staged[start + i]) : ~0ull;
+#pragma unroll
+    for (int i = 0; i < kSmall; ++i) {
+      if ((uint32_t)i >= n) break;
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i];
+      if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
+    }
+  }
+  // every lane of the wave is still here: the mid-size buckets, one by one
+  uint64_t mm = __ballot(n > (uint32_t)kSmall && n <= kMid);
   const uint32_t R = (uint32_t)a.R;
-  const uint32_t waves = gridDim.x * (blockDim.x / kWave);
-  for (uint32_t w = blockIdx.x * (blockDim.x / kWave) + (threadIdx.x >> 6); w < len; w += waves) {
-    const uint4 e = a.work[w];
-    const uint32_t bk = e.x, n = e.z;
-    const uint32_t t = bk / a.M;
-    const uint64_t v = lane < n ? priority(a.s_p, t, (uint32_t)a.staged[e.y + lane]) : ~0ull;
+  while (mm) {
+    const uint32_t src = (uint32_t)__ffsll((unsigned long long)mm) - 1;
+    mm &= mm - 1;
+    const uint32_t bn = (uint32_t)__builtin_amdgcn_readlane((int)n, (int)src);
+    const uint32_t bs = (uint32_t)__builtin_amdgcn_readlane((int)start, (int)src);
+    const uint64_t bb = bk - lane + src;
+    const uint32_t t = (uint32_t)(bb / a.M);
+    const uint64_t v = lane < bn ? priority(a.s_p, t, (uint32_t)a.staged[bs + lane]) : ~0ull;
     const uint64_t sorted = wave_bitonic_sort(v);
-    if (lane < n && lane < R) a.ids[(uint64_t)bk * R + lane] = (int32_t)(uint32_t)sorted;
+    if (lane < bn && lane < R) a.ids[bb * R + lane] = (int32_t)(uint32_t)sorted;
   }
 }
 
@@ -467,7 +468,6 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.M = c.M;
   a.R = c.R;
   hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bucket_select_mid_kernel, dim3(device_info().cus * 16), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
   return hipGetLastError();
 }
