@@ -68,13 +68,23 @@ struct PartArgs {
   uint32_t np, M, ch, n_chunks, n_slices, slice_vecs;
 };
 
+// Workgroups go to the 8 XCDs round-robin by blockIdx.x.  This bijection
+// renumbers them so that consecutive logical blocks run on one XCD: the
+// slices of one (table, chunk) then write their interleaved runs of `staged`
+// through the same L2, where the partial lines merge.
+__device__ __forceinline__ uint32_t xcd_local_block(uint32_t p, uint32_t g) {
+  const uint32_t x = p & 7, q = g >> 3, r = g & 7;
+  return x * q + (x < r ? x : r) + (p >> 3);
+}
+
 // Block (t, chunk, slice): histogram of the keys of table t inside the chunk,
 // over the slice's rows, in LDS.
 __global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
   extern __shared__ uint32_t h[];
-  const uint32_t sl = blockIdx.x % a.n_slices;
-  const uint32_t ck = (blockIdx.x / a.n_slices) % a.n_chunks;
-  const uint32_t t = blockIdx.x / (a.n_slices * a.n_chunks);
+  const uint32_t lb = xcd_local_block(blockIdx.x, gridDim.x);
+  const uint32_t sl = lb % a.n_slices;
+  const uint32_t ck = (lb / a.n_slices) % a.n_chunks;
+  const uint32_t t = lb / (a.n_slices * a.n_chunks);
   const uint32_t lo = ck * a.ch;
   for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads) h[j] = 0;
   __syncthreads();
@@ -100,9 +110,10 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
 // (bucket, slice) run; LDS cursors start at partoff.
 __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) {
   extern __shared__ uint32_t cur[];
-  const uint32_t sl = blockIdx.x % a.n_slices;
-  const uint32_t ck = (blockIdx.x / a.n_slices) % a.n_chunks;
-  const uint32_t t = blockIdx.x / (a.n_slices * a.n_chunks);
+  const uint32_t lb = xcd_local_block(blockIdx.x, gridDim.x);
+  const uint32_t sl = lb % a.n_slices;
+  const uint32_t ck = (lb / a.n_slices) % a.n_chunks;
+  const uint32_t t = lb / (a.n_slices * a.n_chunks);
   const uint32_t lo = ck * a.ch;
   const uint64_t b0 = (uint64_t)t * a.M + lo;
   for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads)
