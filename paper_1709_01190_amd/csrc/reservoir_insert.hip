@@ -239,29 +239,63 @@ __device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
   return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Ascending sort of one 64-bit value per lane across the 64 lanes.
-__device__ __forceinline__ uint64_t wave_bitonic_sort(uint64_t v) {
+// Ascending sort of one 64-bit value per lane within each aligned segment of
+// SEG lanes (SEG a power of two <= 64), all segments at once.
+template <uint32_t SEG>
+__device__ __forceinline__ uint64_t segment_bitonic_sort(uint64_t v) {
   const uint32_t lane = threadIdx.x & 63;
 #pragma unroll
-  for (uint32_t k = 2; k <= 64; k <<= 1) {
+  for (uint32_t k = 2; k <= SEG; k <<= 1) {
 #pragma unroll
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
       const uint64_t o = xor_lane64(v, j);
       const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
-      v = (((lane & j) == 0) == ((lane & k) == 0)) ? mn : mx;
+      const bool up = k == SEG || (lane & k) == 0;
+      v = (((lane & j) == 0) == up) ? mn : mx;
     }
   }
   return v;
 }
 
+// The wave sorts the buckets of its lanes whose sizes are in (lo, SEG], 64 /
+// SEG at a time, one per segment of SEG lanes, one arrival per lane, and
+// writes their reservoirs.  `n`, `start` are the bucket size and first staged
+// slot of each lane's own bucket bk.
+template <uint32_t SEG>
+__device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, uint64_t bk, uint32_t n,
+                                                         uint32_t start, uint32_t lo) {
+  constexpr uint32_t G = 64 / SEG;
+  const uint32_t lane = threadIdx.x & 63, seg = lane / SEG, sl = lane % SEG;
+  const uint32_t R = (uint32_t)a.R;
+  uint64_t mm = __ballot(n > lo && n <= SEG);
+  while (mm) {
+    // pop up to G buckets; segment g takes the g-th (segments past the last get none)
+    uint32_t my_src = 64;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+      const uint32_t src = mm ? (uint32_t)__ffsll((unsigned long long)mm) - 1 : 64u;
+      if (mm) mm &= mm - 1;
+      if (seg == g) my_src = src;
+    }
+    const bool has = my_src < 64;
+    const uint32_t bn = (uint32_t)__shfl((int)n, has ? (int)my_src : 0, 64);
+    const uint32_t bs = (uint32_t)__shfl((int)start, has ? (int)my_src : 0, 64);
+    const uint64_t bb = bk - lane + (has ? my_src : 0);
+    const uint32_t t = (uint32_t)(bb / a.M);
+    const bool live = has && sl < bn;
+    const uint64_t v = live ? priority(a.s_p, t, (uint32_t)a.staged[bs + sl]) : ~0ull;
+    const uint64_t sorted = segment_bitonic_sort<SEG>(v);
+    if (live && sl < R) a.ids[bb * R + sl] = (int32_t)(uint32_t)sorted;
+  }
+}
+
 // Thread per bucket.  Buckets with at most kSmall arrivals: each thread ranks
 // its arrivals against each other in registers.  Buckets with kSmall < n <=
-// kMid: the wave takes them one after another, one arrival per lane, and
-// sorts across the lanes in registers.  Larger buckets are listed (with
+// kMid: the wave sorts them in registers, one arrival per lane, four at a
+// time up to 16 arrivals and two at a time up to 32.  Larger buckets are listed (with
 // their start and size) for the LDS kernel; they are rare, so their appends
 // are few.
 __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
-  const uint32_t lane = threadIdx.x & 63;
   const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = bk < a.n_buckets;
   const uint32_t n = in ? a.counts[bk] : 0u;
@@ -284,20 +318,11 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
       if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
     }
   }
-  // every lane of the wave is still here: the mid-size buckets, one by one
-  uint64_t mm = __ballot(n > (uint32_t)kSmall && n <= kMid);
-  const uint32_t R = (uint32_t)a.R;
-  while (mm) {
-    const uint32_t src = (uint32_t)__ffsll((unsigned long long)mm) - 1;
-    mm &= mm - 1;
-    const uint32_t bn = (uint32_t)__builtin_amdgcn_readlane((int)n, (int)src);
-    const uint32_t bs = (uint32_t)__builtin_amdgcn_readlane((int)start, (int)src);
-    const uint64_t bb = bk - lane + src;
-    const uint32_t t = (uint32_t)(bb / a.M);
-    const uint64_t v = lane < bn ? priority(a.s_p, t, (uint32_t)a.staged[bs + lane]) : ~0ull;
-    const uint64_t sorted = wave_bitonic_sort(v);
-    if (lane < bn && lane < R) a.ids[bb * R + lane] = (int32_t)(uint32_t)sorted;
-  }
+  // every lane of the wave is still here: the mid-size buckets, several per
+  // wave when they are small enough
+  sort_buckets_by_segments<16>(a, bk, n, start, (uint32_t)kSmall);
+  sort_buckets_by_segments<32>(a, bk, n, start, 16u);
+  sort_buckets_by_segments<64>(a, bk, n, start, 32u);
 }
 
 // One wave per large bucket (n > 64).
