@@ -415,7 +415,10 @@ Geo geometry(const Cfg& c, int64_t n_rows) {
   g.ch = c.M < kChunk ? c.M : kChunk;
   g.n_chunks = c.M / g.ch;
   const uint32_t base_blocks = (uint32_t)c.L * g.n_chunks;
-  uint32_t s = (1024 + base_blocks - 1) / base_blocks;   // aim for ~1024 blocks
+  // about one partition block per CU: more row slices interleave more runs
+  // of `staged` (partial-line writes), fewer leave CUs idle
+  const uint32_t cus = (uint32_t)device_info().cus;
+  uint32_t s = (cus + base_blocks - 1) / base_blocks;
   const uint32_t max_s = g.np / 16384 > 1 ? g.np / 16384 : 1;  // slices of >= 16384 rows
   if (s > max_s) s = max_s;
   if (s < 1) s = 1;
