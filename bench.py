@@ -44,8 +44,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving", "uneven"])
+    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving", "uneven", "append"])
     ap.add_argument("--queries", type=int, default=1_000_000, help="uneven: queries in the batch")
+    ap.add_argument("--batches", type=int, default=24, help="append: batches the index is grown in")
     ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
                     help="serving: offered queries per second, comma separated")
     ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
@@ -64,11 +65,11 @@ def main():
     if args.copy_mib:
         copy_calibration(args.copy_mib)
         return
-    if args.workload in ("serving", "uneven"):
+    if args.workload in ("serving", "uneven", "append"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
             sys.exit(2)
-        (serving_bench if args.workload == "serving" else uneven_bench)(args)
+        {"serving": serving_bench, "uneven": uneven_bench, "append": append_bench}[args.workload](args)
         return
 
     if args.gpus != 1:
@@ -429,6 +430,82 @@ def uneven_bench(args):
         "tuning": best.as_dict(),
         "index_build_ms": round(med(build_ms), 3),
         "identical_lists": same,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def append_bench(args):
+    """Incremental insertion: the URL-shaped index (2.4M rows; K=5 L=32 b=3
+    R=64) grown by flash_build_index_append in equal batches, against one
+    flash_build_index over all rows; the tables must be identical."""
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import datagen, flash
+
+    torch.cuda.set_device(0)
+    spec = datagen.URL
+    if args.rows:
+        spec = datagen.scaled(spec, args.rows)
+    n = spec.n_rows
+    rp, ci = datagen.make_rows(spec, 1, device="cuda")
+    p = flash.flash_params.make(5, 32, 3, 64, seed=1)
+    stream = torch.cuda.current_stream()
+    c1, i1 = flash.alloc_index(p)
+    ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=n)
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return out
+
+    one = timed(lambda: flash.flash_build_index(p, rp, ci, c1, i1, ws, stream=stream), args.warmup + args.steps)
+    del ws
+    cuts = [round(n * j / args.batches) for j in range(args.batches + 1)]
+    batches = []
+    for lo, hi in zip(cuts, cuts[1:]):
+        a, b = int(rp[lo]), int(rp[hi])
+        batches.append((lo, (rp[lo:hi + 1] - a).contiguous(), ci[a:b]))
+    bws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=max(hi - lo for lo, hi in zip(cuts, cuts[1:])))
+    c2, i2 = flash.alloc_index(p)
+
+    def grow():
+        c2.zero_()
+        for lo, brp, bci in batches:
+            flash.flash_build_index_append(p, brp, bci, lo, c2, i2, bws, stream=stream)
+
+    grown = timed(grow, args.warmup + args.steps)
+    L, M, R = p.L, p.M, p.R
+    same_counts = bool(torch.equal(c1, c2))
+    occ = torch.clamp(c1.view(L, M).long(), max=R)
+    mask = torch.arange(R, device="cuda")[None, None, :] < occ[:, :, None]
+    same_ids = bool(torch.equal(i1.view(L, M, R)[mask], i2.view(L, M, R)[mask]))
+    t_one = float(np.median(one[args.warmup:]))
+    t_grow = float(np.median(grown[args.warmup:]))
+    out = {
+        "metric": "incremental insertion rows per second (url-shape index grown in batches)",
+        "value": round(n / (t_grow / 1e3), 1),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(t_grow, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "url-shaped incremental build", "rows": n, "nnz": int(ci.numel()),
+                   "K": 5, "L": 32, "bits_per_hash": 3, "R": 64, "batches": args.batches},
+        "one_shot_build_ms": round(t_one, 3),
+        "grown_build_ms": round(t_grow, 3),
+        "identical_tables": same_counts and same_ids,
     }
     print(json.dumps(out), flush=True)
 

@@ -123,6 +123,28 @@ FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t n
                                 uint32_t *counts, int32_t *ids, uint32_t *keys_out,
                                 void *workspace, size_t workspace_bytes, void *stream);
 
+/* Incremental insertion into a resident index (Sec. 3.2 item 2; Sec. 3.4:
+ * rows are added independently).  Adds n_rows rows, given by their keys
+ * (device uint32[n_rows][L], as flash_hash writes them), with ids id_base ..
+ * id_base + n_rows - 1 to the index in counts/ids, which already holds rows
+ * with other ids (a fresh index: counts all zero).  A reservoir keeps the R
+ * lowest priorities of its arrivals, so after any sequence of calls the
+ * index is bit-identical (counts and occupied slots) to one
+ * flash_insert_keys over all rows added, whatever the batching and order.
+ * Ids must not repeat across calls (not checked).  0 <= id_base and
+ * id_base + n_rows < 2^31.  Workspace: FLASH_OP_INSERT for n_rows.  Calls on
+ * one index must be ordered on one stream; n_rows = 0 enqueues nothing. */
+FLASH_API int flash_insert_keys_append(const flash_params *p, int64_t n_rows, const uint32_t *keys,
+                                       int64_t id_base, uint32_t *counts, int32_t *ids,
+                                       void *workspace, size_t workspace_bytes, void *stream);
+
+/* flash_insert_keys_append from CSR rows: flash_hash into the workspace, then
+ * the append.  Workspace: FLASH_OP_BUILD for n_rows. */
+FLASH_API int flash_build_index_append(const flash_params *p, int64_t n_rows, int64_t nnz,
+                                       const int64_t *row_ptr, const int32_t *col_idx,
+                                       int64_t id_base, uint32_t *counts, int32_t *ids,
+                                       void *workspace, size_t workspace_bytes, void *stream);
+
 /* Alg. 3 (querying phase) from precomputed keys qkeys uint32[n_queries][L].
  * cnt(x) = number of tables whose bucket qkeys[q][t] keeps id x; ids equal to
  * self_ids[q] (if self_ids is not NULL and the entry is >= 0) are left out.

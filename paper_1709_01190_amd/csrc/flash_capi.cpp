@@ -216,7 +216,61 @@ FLASH_API int flash_insert_keys(const flash_params* p, int64_t n_rows, const uin
   if (!workspace || workspace_bytes < need)
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_INSERT)");
   const InsertWs w = insert_ws_carve(c, n_rows, workspace);
-  hipError_t e = launch_insert(c, n_rows, keys, counts, ids, w, (hipStream_t)stream);
+  hipError_t e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, w, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
+}
+
+namespace {
+
+int check_append(const Cfg& c, int64_t n_rows, int64_t id_base) {
+  if (id_base < 0) return fail(FLASH_EINVAL, "id_base must be >= 0");
+  if (n_rows < 0) return fail(FLASH_EINVAL, "n_rows must be >= 0");
+  if (id_base + n_rows > ((int64_t)1 << 31) - 1) return fail(FLASH_EINVAL, "id_base + n_rows must be < 2^31");
+  if ((uint64_t)n_rows * (uint64_t)c.L >= (uint64_t)1 << 32)
+    return fail(FLASH_EINVAL, "n_rows * L must be < 2^32");
+  return FLASH_OK;
+}
+
+}  // namespace
+
+FLASH_API int flash_insert_keys_append(const flash_params* p, int64_t n_rows, const uint32_t* keys,
+                                       int64_t id_base, uint32_t* counts, int32_t* ids, void* workspace,
+                                       size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_append(c, n_rows, id_base))) return r;
+  if (!counts || !ids || (n_rows > 0 && !keys)) return fail(FLASH_EINVAL, "NULL array");
+  const size_t need = insert_ws_bytes(c, n_rows);
+  if (n_rows > 0 && (!workspace || workspace_bytes < need))
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_INSERT)");
+  if (n_rows == 0) return FLASH_OK;
+  const InsertWs w = insert_ws_carve(c, n_rows, workspace);
+  hipError_t e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, counts, ids, w, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
+}
+
+FLASH_API int flash_build_index_append(const flash_params* p, int64_t n_rows, int64_t nnz,
+                                       const int64_t* row_ptr, const int32_t* col_idx, int64_t id_base,
+                                       uint32_t* counts, int32_t* ids, void* workspace,
+                                       size_t workspace_bytes, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_append(c, n_rows, id_base))) return r;
+  if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
+  if (!counts || !ids) return fail(FLASH_EINVAL, "NULL index array");
+  const size_t kb = keys_bytes(c, n_rows);
+  const size_t need = kb + insert_ws_bytes(c, n_rows);
+  if (n_rows > 0 && (!workspace || workspace_bytes < need))
+    return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_BUILD)");
+  if (n_rows == 0) return FLASH_OK;
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* keys = (uint32_t*)workspace;
+  hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, counts, ids, insert_ws_carve(c, n_rows, (char*)workspace + kb),
+                    s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
@@ -239,7 +293,7 @@ FLASH_API int flash_build_index(const flash_params* p, int64_t n_rows, int64_t n
   hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   const InsertWs w = insert_ws_carve(c, n_rows, (char*)workspace + kb);
-  e = launch_insert(c, n_rows, keys, counts, ids, w, s);
+  e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
@@ -361,7 +415,7 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   char* rest = (char*)workspace + kb;
   hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_insert(c, n_rows, keys, counts, ids, insert_ws_carve(c, n_rows, rest), s);
+  e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, insert_ws_carve(c, n_rows, rest), s);
   if (e != hipSuccess) return hip_fail(e, "reservoir_insert");
   e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, nullptr, out_ids, out_counts,
                    query_ws_carve(c, n_rows, rest), s);

@@ -44,14 +44,17 @@ struct InsertWs {
   uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)
   uint32_t* partoff;    // [L * M * S]    exclusive prefix of part
   uint32_t* seg;        // [L * M]        first staged slot of each bucket
+  uint32_t* newcnt;     // [L * M]        the batch's arrivals per bucket
   uint4* work;          // [L * M]        {bucket, start, size} of the large buckets
   uint32_t* tile_sums;  // [tiles + 1]    scan carries
   uint32_t* wl_len;     // [2]
 };
 size_t insert_ws_bytes(const Cfg& c, int64_t n_rows);
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws);
-hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t* counts,
-                         int32_t* ids, const InsertWs& w, hipStream_t s);
+// Rows of this batch get ids id_base + row.  append: merge into the
+// reservoirs and counts already in ids/counts (else they are replaced).
+hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t id_base, bool append,
+                         uint32_t* counts, int32_t* ids, const InsertWs& w, hipStream_t s);
 
 // ---- query (count_topk.hip)
 struct QueryWs {

@@ -66,6 +66,7 @@ struct PartArgs {
   const uint32_t* partoff; // [L * M * S]
   int32_t* staged;
   uint32_t np, M, ch, n_chunks, n_slices, slice_vecs;
+  uint32_t id_base;        // id of row 0 of this batch
 };
 
 // Workgroups go to the 8 XCDs round-robin by blockIdx.x.  This bijection
@@ -129,19 +130,20 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t d = kk[j] - lo;
-      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(4 * v + (uint32_t)j);
+      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + 4 * v + (uint32_t)j);
     }
   }
 }
 
-// counts[b] = sum of the bucket's slice counts, seg[b] = its first staged slot.
+// newcnt[b] = the batch's arrivals in bucket b (sum over its slices), seg[b]
+// = their first staged slot.
 __global__ void bucket_totals_kernel(const uint32_t* part, const uint32_t* partoff, uint64_t nb,
-                                     uint32_t n_slices, uint32_t* counts, uint32_t* seg) {
+                                     uint32_t n_slices, uint32_t* newcnt, uint32_t* seg) {
   for (uint64_t b = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; b < nb;
        b += (uint64_t)gridDim.x * blockDim.x) {
     uint32_t c = 0;
     for (uint32_t s = 0; s < n_slices; ++s) c += part[b * n_slices + s];
-    counts[b] = c;
+    newcnt[b] = c;
     seg[b] = partoff[b * n_slices];
   }
 }
@@ -212,18 +214,27 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
 }
 
 struct SelectArgs {
-  const uint32_t* counts;
-  const uint32_t* seg;
+  uint32_t* counts;        // in (when appending: the index's counts) and out
+  const uint32_t* newcnt;  // the batch's arrivals per bucket
+  const uint32_t* seg;     // their first staged slot
   const int32_t* staged;
   int32_t* ids;
-  uint4* work;          // [nb] {bucket, first staged slot, arrivals, 0}: mid-size
-                        // buckets from the front, large buckets from the back
+  uint4* work;          // [nb] {bucket, first staged slot, candidates, old slots}
+                        // of the large buckets, from the back
   uint32_t* wl_len;     // [2] [1]: large buckets listed ([0] unused)
   uint64_t n_buckets;
   uint64_t s_p;
   uint32_t M;
   int R;
+  int append;           // 1: merge with the reservoirs already in ids/counts
 };
+
+// Candidate i of bucket bk: its first `occ` are the ids already in the
+// reservoir (appending), the rest the batch's arrivals.
+__device__ __forceinline__ uint32_t candidate(const SelectArgs& a, uint64_t bk, uint32_t start, uint32_t occ,
+                                              uint32_t i) {
+  return i < occ ? (uint32_t)a.ids[bk * (uint64_t)a.R + i] : (uint32_t)a.staged[start + i - occ];
+}
 
 constexpr uint32_t kMid = 64;  // arrivals handled by one wave in registers
 
@@ -263,7 +274,7 @@ __device__ __forceinline__ uint64_t segment_bitonic_sort(uint64_t v) {
 // slot of each lane's own bucket bk.
 template <uint32_t SEG>
 __device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, uint64_t bk, uint32_t n,
-                                                         uint32_t start, uint32_t lo) {
+                                                         uint32_t start, uint32_t occ, uint32_t lo) {
   constexpr uint32_t G = 64 / SEG;
   const uint32_t lane = threadIdx.x & 63, seg = lane / SEG, sl = lane % SEG;
   const uint32_t R = (uint32_t)a.R;
@@ -280,10 +291,11 @@ __device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, ui
     const bool has = my_src < 64;
     const uint32_t bn = (uint32_t)__shfl((int)n, has ? (int)my_src : 0, 64);
     const uint32_t bs = (uint32_t)__shfl((int)start, has ? (int)my_src : 0, 64);
+    const uint32_t bo = (uint32_t)__shfl((int)occ, has ? (int)my_src : 0, 64);
     const uint64_t bb = bk - lane + (has ? my_src : 0);
     const uint32_t t = (uint32_t)(bb / a.M);
     const bool live = has && sl < bn;
-    const uint64_t v = live ? priority(a.s_p, t, (uint32_t)a.staged[bs + sl]) : ~0ull;
+    const uint64_t v = live ? priority(a.s_p, t, candidate(a, bb, bs, bo, sl)) : ~0ull;
     const uint64_t sorted = segment_bitonic_sort<SEG>(v);
     if (live && sl < R) a.ids[bb * R + sl] = (int32_t)(uint32_t)sorted;
   }
@@ -298,17 +310,22 @@ __device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, ui
 __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
   const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool in = bk < a.n_buckets;
-  const uint32_t n = in ? a.counts[bk] : 0u;
+  const uint32_t R = (uint32_t)a.R;
+  const uint32_t nn = in ? a.newcnt[bk] : 0u;
+  const uint32_t old = (in && a.append) ? a.counts[bk] : 0u;
+  const uint32_t occ = old < R ? old : R;   // reservoir slots that take part
+  const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
   const uint32_t start = in ? a.seg[bk] : 0u;
+  if (in) a.counts[bk] = old + nn;
   const bool big = n > kMid;
   const uint32_t pb = wave_append(&a.wl_len[1], big);
-  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, 0u);
+  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, occ);
   if (n >= 1 && n <= (uint32_t)kSmall) {
     const uint32_t t = (uint32_t)(bk / a.M);
     uint64_t pk[kSmall];
 #pragma unroll
     for (int i = 0; i < kSmall; ++i)
-      pk[i] = (uint32_t)i < n ? priority(a.s_p, t, (uint32_t)a.staged[start + i]) : ~0ull;
+      pk[i] = (uint32_t)i < n ? priority(a.s_p, t, candidate(a, bk, start, occ, (uint32_t)i)) : ~0ull;
 #pragma unroll
     for (int i = 0; i < kSmall; ++i) {
       if ((uint32_t)i >= n) break;
@@ -320,9 +337,9 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
   }
   // every lane of the wave is still here: the mid-size buckets, several per
   // wave when they are small enough
-  sort_buckets_by_segments<16>(a, bk, n, start, (uint32_t)kSmall);
-  sort_buckets_by_segments<32>(a, bk, n, start, 16u);
-  sort_buckets_by_segments<64>(a, bk, n, start, 32u);
+  sort_buckets_by_segments<16>(a, bk, n, start, occ, (uint32_t)kSmall);
+  sort_buckets_by_segments<32>(a, bk, n, start, occ, 16u);
+  sort_buckets_by_segments<64>(a, bk, n, start, occ, 32u);
 }
 
 // One wave per large bucket (n > 64).
@@ -336,13 +353,12 @@ __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
                                                                        : kWaveCap;
   for (uint32_t w = blockIdx.x; w < len; w += gridDim.x) {
     const uint4 e = a.work[a.n_buckets - 1 - w];
-    const uint32_t bk = e.x, n = e.z;
+    const uint32_t bk = e.x, n = e.z, occ = e.w;
     const uint32_t t = bk / a.M;
-    const int32_t* src = a.staged + e.y;
     uint32_t c;
     if (n <= sort_all) {
       c = n;
-      for (uint32_t i = lane; i < n; i += kWave) buf[i] = priority(a.s_p, t, (uint32_t)src[i]);
+      for (uint32_t i = lane; i < n; i += kWave) buf[i] = priority(a.s_p, t, candidate(a, bk, e.y, occ, i));
     } else {
       // keep priorities whose top 32 bits are below thr; aim for
       // min(2R, (R + cap) / 2) of them, bisect until R <= kept <= cap
@@ -355,7 +371,7 @@ __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
         if (lane == 0) cnt_sh = 0;
         __syncthreads();
         for (uint32_t i = lane; i < n; i += kWave) {
-          const uint64_t pk = priority(a.s_p, t, (uint32_t)src[i]);
+          const uint64_t pk = priority(a.s_p, t, candidate(a, bk, e.y, occ, i));
           if ((pk >> 32) < thr) {
             const uint32_t pos = atomicAdd(&cnt_sh, 1u);
             if (pos < kWaveCap) buf[pos] = pk;
@@ -380,6 +396,7 @@ __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
     for (uint32_t i = c + lane; i < P; i += kWave) buf[i] = ~0ull;
     __syncthreads();
     block64_bitonic_sort(buf, P);
+    // every candidate was read above: the reservoir can be overwritten
     const uint32_t keep = n < R ? n : R;
     for (uint32_t i = lane; i < keep; i += kWave)
       a.ids[(uint64_t)bk * R + i] = (int32_t)(uint32_t)buf[i];
@@ -436,7 +453,7 @@ size_t insert_ws_bytes(const Cfg& c, int64_t n_rows) {
   const Geo g = geometry(c, n_rows);
   const uint64_t ne = (uint64_t)(n_rows > 0 ? n_rows : 1) * c.L;
   return align256(4 * (uint64_t)c.L * g.np) + align256(4 * ne) + 2 * align256(4 * g.nparts) +
-         align256(4 * g.nb) + align256(16 * g.nb) + align256(4 * (g.tiles + 1)) + align256(8);
+         2 * align256(4 * g.nb) + align256(16 * g.nb) + align256(4 * (g.tiles + 1)) + align256(8);
 }
 
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
@@ -454,6 +471,8 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
   p += align256(4 * g.nparts);
   w.seg = (uint32_t*)p;
   p += align256(4 * g.nb);
+  w.newcnt = (uint32_t*)p;
+  p += align256(4 * g.nb);
   w.work = (uint4*)p;
   p += align256(16 * g.nb);
   w.tile_sums = (uint32_t*)p;
@@ -462,12 +481,12 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
   return w;
 }
 
-hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t* counts,
-                         int32_t* ids, const InsertWs& w, hipStream_t s) {
+hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t id_base, bool append,
+                         uint32_t* counts, int32_t* ids, const InsertWs& w, hipStream_t s) {
   const Geo g = geometry(c, n_rows);
   hipError_t e;
+  if (n_rows <= 0) return append ? hipSuccess : launch_fill_u32(counts, g.nb, 0u, s);
   if ((e = launch_fill_u32(w.wl_len, 2, 0u, s)) != hipSuccess) return e;
-  if (n_rows <= 0) return launch_fill_u32(counts, g.nb, 0u, s);
   // table-major keys
   hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
                      (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t);
@@ -482,6 +501,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   pa.n_chunks = g.n_chunks;
   pa.n_slices = g.n_slices;
   pa.slice_vecs = g.slice_vecs;
+  pa.id_base = id_base;
   const uint32_t blocks = (uint32_t)c.L * g.n_chunks * g.n_slices;
   const size_t lds = sizeof(uint32_t) * g.ch;
   hipLaunchKernelGGL(part_count_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
@@ -493,10 +513,11 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   hipLaunchKernelGGL(scan_tiles_kernel, dim3(tiles), dim3(kScanThreads), 0, s, w.part, g.nparts,
                      w.tile_sums, w.partoff);
   hipLaunchKernelGGL(bucket_totals_kernel, dim3(grid_for(g.nb, 256, 16)), dim3(256), 0, s, w.part,
-                     w.partoff, g.nb, g.n_slices, counts, w.seg);
+                     w.partoff, g.nb, g.n_slices, w.newcnt, w.seg);
   hipLaunchKernelGGL(part_scatter_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
   SelectArgs a;
   a.counts = counts;
+  a.newcnt = w.newcnt;
   a.seg = w.seg;
   a.staged = w.staged;
   a.ids = ids;
@@ -506,6 +527,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.s_p = c.seeds.s_p;
   a.M = c.M;
   a.R = c.R;
+  a.append = append ? 1 : 0;
   hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
   return hipGetLastError();

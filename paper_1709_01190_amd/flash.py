@@ -89,6 +89,8 @@ def lib():
                                     _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
                             ctypes.c_size_t, _VP],
+        "flash_insert_keys_append": [P, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_build_index_append": [P, _I64, _I64, _VP, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_get_tuning": [ctypes.POINTER(flash_tuning)],
         "flash_set_tuning": [ctypes.POINTER(flash_tuning)],
         "flash_autotune_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP,
@@ -198,6 +200,29 @@ def flash_build_index(p, row_ptr, col_idx, counts, ids, workspace, keys_out=None
     _check(lib().flash_build_index(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx),
                                    _p(counts), _p(ids), _p(keys_out), _p(workspace),
                                    workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_insert_keys_append(p, keys, id_base, counts, ids, workspace, stream=None):
+    n = keys.numel() // p.L
+    ce, ie = flash_index_elems(p)
+    _need(counts, ce, _U32, "counts")
+    _need(ids, ie, (torch.int32,), "ids")
+    _check(lib().flash_insert_keys_append(ctypes.byref(p), n, _p(keys) if n else None, id_base,
+                                          _p(counts), _p(ids), _p(workspace) if workspace is not None else None,
+                                          workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                          _s(stream)))
+
+
+def flash_build_index_append(p, row_ptr, col_idx, id_base, counts, ids, workspace, stream=None):
+    n = row_ptr.numel() - 1
+    ce, ie = flash_index_elems(p)
+    _need(counts, ce, _U32, "counts")
+    _need(ids, ie, (torch.int32,), "ids")
+    _check(lib().flash_build_index_append(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr) if n else None,
+                                          _p(col_idx) if col_idx.numel() else None, id_base, _p(counts), _p(ids),
+                                          _p(workspace) if workspace is not None else None,
+                                          workspace.numel() * workspace.element_size() if workspace is not None else 0,
+                                          _s(stream)))
 
 
 def flash_query_keys(p, counts, ids, n_indexed, qkeys, k, out_ids, out_counts, workspace,

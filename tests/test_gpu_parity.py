@@ -588,3 +588,93 @@ def test_clicklog_full_size_uneven(fl, orc):
     wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp_d.cpu().numpy(), qci_d.cpu().numpy()),
                              kq.numpy(), 100)
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+# ------------------------------------------------------------------ incremental insertion
+
+def _append_batches(fl, p, keys_np, cuts, order, first_fresh=False):
+    """Index built by appending row ranges [cuts[i], cuts[i+1]) in the given
+    order into a zeroed index (or, with first_fresh, the first range by
+    flash_insert_keys, which numbers rows from 0, so that range must start at
+    row 0, and the rest appended)."""
+    import torch
+    counts, ids = fl.alloc_index(p)
+    counts.zero_()
+    for j, i in enumerate(order):
+        lo, hi = cuts[i], cuts[i + 1]
+        part = dev(np.ascontiguousarray(keys_np[lo:hi]).astype(np.uint32), torch.int32)
+        ws = fl.alloc_workspace(fl.OP_INSERT, p, n_rows=hi - lo) if hi > lo else None
+        if first_fresh and j == 0:
+            assert lo == 0
+            fl.flash_insert_keys(p, part, counts, ids, ws)
+        else:
+            fl.flash_insert_keys_append(p, part, lo, counts, ids, ws)
+    torch.cuda.synchronize()
+    return counts, ids
+
+
+def test_append_batches_equal_one_build(fl, orc, tiny_index):
+    # any batching and order of appends gives the one-shot build's tables
+    say("append tiny")
+    p, op, rp, ci, keys, counts0, ids0, ocounts, oids = tiny_index
+    n = keys.shape[0]
+    cuts = [0, 3000, 3001, 3001, 7000, n]
+    for order, fresh in (([0, 1, 2, 3, 4], False), ([3, 0, 4, 2, 1], False), ([0, 4, 2, 3, 1], True)):
+        say("append order", order, "fresh first" if fresh else "")
+        c, i = _append_batches(fl, p, keys, cuts, order, first_fresh=fresh)
+        occupied_equal(u32(c), i32(i), ocounts.reshape(-1), oids.reshape(-1), p.L, p.M, p.R)
+
+
+@pytest.mark.parametrize("R", [1, 4, 32, 256])
+def test_append_into_full_reservoirs(fl, orc, R):
+    # saturated buckets: every path of the select merges old slots with new
+    # arrivals (thread, lane segments, wave sort, priority threshold)
+    say("append heavy buckets R", R)
+    rng = np.random.default_rng(100 + R)
+    K, L, b = 2, 3, 5
+    M = 1 << (K * b)
+    sizes = [1, 5, 9, 20, 40, 63, 64, 65, R + 1, 2 * R + 1, 3000, 40000]
+    cols = []
+    for t in range(L):
+        col = np.concatenate([np.full(s, (i * 5 + t) % M, dtype=np.uint32) for i, s in enumerate(sizes)])
+        rng.shuffle(col)
+        cols.append(col)
+    n = max(len(c) for c in cols)
+    km = np.full((n, L), EMPTY, dtype=np.uint32)
+    for t in range(L):
+        km[:len(cols[t]), t] = cols[t]
+    op = orc.params(K, L, b, R, seed=R + 11)
+    ocounts, oids = orc.build_tables(op, km)
+    p = fl.flash_params.make(K, L, b, R, seed=R + 11)
+    cuts = [0, 7, 500, 20000, n // 2, n]
+    c, i = _append_batches(fl, p, km, cuts, [2, 0, 4, 1, 3])
+    occupied_equal(u32(c), i32(i), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+
+
+def test_append_csr_batches_then_query(fl, orc):
+    # a URL-shaped index grown from CSR batches, then queried
+    import torch
+    from paper_1709_01190_amd import datagen
+    say("append url csr")
+    spec = datagen.scaled(datagen.URL, 120_000)
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
+    K, L, b, R = 5, 32, 3, 64
+    p = fl.flash_params.make(K, L, b, R, seed=1)
+    op = orc.params(K, L, b, R, seed=1)
+    okeys = orc.doph(op, rp, ci)
+    ocounts, oids = orc.build_tables(op, okeys)
+    counts, ids = fl.alloc_index(p)
+    counts.zero_()
+    cuts = [0, 50_000, 50_001, 90_000, spec.n_rows]
+    for lo, hi in zip(cuts, cuts[1:]):
+        brp = dev((rp[lo:hi + 1] - rp[lo]).astype(np.int64))
+        bci = dev(ci[rp[lo]:rp[hi]])
+        ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=hi - lo)
+        fl.flash_build_index_append(p, brp, bci, lo, counts, ids, ws)
+    torch.cuda.synchronize()
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
+    sample = np.arange(0, spec.n_rows, 97)
+    gi, gc = gpu_query(fl, p, counts, ids, spec.n_rows, okeys[sample], 20, sample.astype(np.int32))
+    wi, wc = orc.query(op, ocounts, oids, okeys[sample], 20, self_ids=sample.astype(np.int32))
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)

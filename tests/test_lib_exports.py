@@ -118,3 +118,20 @@ def test_tuning_is_checked_and_restorable(fl):
         fl.flash_set_tuning(t)
     fl.flash_set_tuning(None)
     assert fl.flash_get_tuning().as_dict() == d
+
+
+def test_append_arguments_are_checked_on_the_host(fl):
+    import torch
+    p = fl.flash_params.make(4, 16, 4, 32)
+    L = fl.lib()
+    for n, base in ((10, -1), (10, (1 << 31) - 5)):
+        r = L.flash_insert_keys_append(ctypes.byref(p), n, ctypes.c_void_p(16), base, ctypes.c_void_p(16),
+                                       ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+        assert r == fl.FLASH_EINVAL
+    # too small a workspace
+    r = L.flash_insert_keys_append(ctypes.byref(p), 1000, ctypes.c_void_p(16), 0, ctypes.c_void_p(16),
+                                   ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None)
+    assert r == fl.FLASH_ENOSPC
+    # nothing to add: nothing enqueued, no workspace needed
+    assert L.flash_insert_keys_append(ctypes.byref(p), 0, None, 5, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                      None, 0, None) == fl.FLASH_OK
