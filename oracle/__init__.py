@@ -9,6 +9,8 @@ What each function follows (arXiv 1709.01190):
   build           Sec. 2.4 / Alg. 1-2 (fixed-size reservoirs, bottom-R reading)
   query           Alg. 3 (gather L reservoirs, KSELECT by count)
   jaccard_knn     Eq. 2 right-hand side (exact Jaccard), for recall
+  rerank          Sec. 4.3 gold standard: exact cosine (Eq. 3) or Jaccard
+                  ordering of candidate lists
 """
 from __future__ import annotations
 
@@ -70,6 +72,9 @@ def lib():
         L.orc_jaccard_knn.restype = None
         L.orc_jaccard_knn.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                       P, ctypes.c_int32, P, P, P]
+        L.orc_rerank.restype = None
+        L.orc_rerank.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int32,
+                                 ctypes.c_int32, P, P]
         L.orc_num_threads.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -176,6 +181,25 @@ def jaccard_knn(row_ptr, col_idx, n_cols, queries, k):
     lib().orc_jaccard_knn(_ptr(row_ptr), _ptr(col_idx), row_ptr.shape[0] - 1, n_cols, q,
                           _ptr(queries), k, _ptr(oi), _ptr(inter), _ptr(uni))
     return oi, inter, uni
+
+
+SIM_COSINE, SIM_JACCARD = 0, 1
+
+
+def rerank(measure, row_ptr, col_idx, q_row_ptr, q_col_idx, cand, k):
+    """Candidates cand[q][:] (ids of rows of row_ptr/col_idx, -1 = none)
+    ordered by exact similarity to query row q (cosine, Eq. 3, or Jaccard)
+    descending, ties by smaller id; first k as (ids int32, intersections
+    int64), padded with (-1, 0)."""
+    row_ptr, col_idx = _csr(row_ptr, col_idx)
+    q_row_ptr, q_col_idx = _csr(q_row_ptr, q_col_idx)
+    cand = np.ascontiguousarray(cand, dtype=np.int32)
+    q, nc = cand.shape
+    oi = np.empty((q, k), dtype=np.int32)
+    inter = np.empty((q, k), dtype=np.int64)
+    lib().orc_rerank(int(measure), _ptr(row_ptr), _ptr(col_idx), q, _ptr(q_row_ptr), _ptr(q_col_idx),
+                     _ptr(cand), nc, k, _ptr(oi), _ptr(inter))
+    return oi, inter
 
 
 def recall_at_k(row_ptr, col_idx, n_cols, queries, found_ids):

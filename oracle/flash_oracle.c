@@ -474,6 +474,106 @@ void orc_jaccard_knn(const int64_t *row_ptr, const int32_t *col_idx, int64_t n_r
     free(rowlen);
 }
 
+/* ---- exact re-rank of candidate lists (Sec. 4.3's gold standard) ------- */
+
+#define ORC_SIM_COSINE 0
+#define ORC_SIM_JACCARD 1
+
+/*
+ * sim1 > sim2 for candidates with intersections i1, i2 and sizes x1, x2
+ * against a query of size nq, exactly.  Jaccard (Eq. 2's right-hand side)
+ * is i / (nq + x - i); cosine for binary vectors (Eq. 3) is i / sqrt(nq x),
+ * compared through its square i^2 / (nq x), which orders the same way; nq
+ * cancels.  A candidate with no common column has similarity 0.
+ */
+static int sim_greater(int measure, int64_t nq, int64_t i1, int64_t x1, int64_t i2, int64_t x2)
+{
+    __int128 a, b;
+    if (i1 == 0) return 0;
+    if (i2 == 0) return 1;
+    if (measure == ORC_SIM_JACCARD) {
+        a = (__int128)i1 * (nq + x2 - i2);
+        b = (__int128)i2 * (nq + x1 - i1);
+    } else {
+        a = (__int128)i1 * i1 * x2;
+        b = (__int128)i2 * i2 * x1;
+    }
+    return a > b;
+}
+
+/*
+ * For each query row q (q_row_ptr / q_col_idx) and its candidate ids
+ * cand[q][0..nc) (rows of row_ptr / col_idx; negative = no candidate):
+ * inter = |q ∩ x| over distinct columns, then the candidates ordered by
+ * similarity descending, ties by smaller id (insertion sort), and the first
+ * k written to out_ids / out_inter, padded with (-1, 0).
+ */
+void orc_rerank(int measure, const int64_t *row_ptr, const int32_t *col_idx, int64_t n_queries,
+                const int64_t *q_row_ptr, const int32_t *q_col_idx, const int32_t *cand, int32_t nc,
+                int32_t k, int32_t *out_ids, int64_t *out_inter)
+{
+    int64_t q;
+#pragma omp parallel for schedule(dynamic, 8)
+    for (q = 0; q < n_queries; q++) {
+        int64_t nq = q_row_ptr[q + 1] - q_row_ptr[q];
+        int32_t *qa = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nq + 1));
+        int32_t *ids = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nc + 1));
+        int64_t *in = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
+        int64_t *sz = (int64_t *)malloc(sizeof(int64_t) * (size_t)(nc + 1));
+        int m = 0, c, j;
+        memcpy(qa, q_col_idx + q_row_ptr[q], sizeof(int32_t) * (size_t)nq);
+        nq = dedup_sorted(qa, nq);
+        for (c = 0; c < nc; c++) {
+            int32_t x = cand[q * nc + c];
+            int64_t nx, i = 0, jj = 0, cnt = 0;
+            int32_t *xa;
+            int pos;
+            if (x < 0) continue;
+            nx = row_ptr[x + 1] - row_ptr[x];
+            xa = (int32_t *)malloc(sizeof(int32_t) * (size_t)(nx + 1));
+            memcpy(xa, col_idx + row_ptr[x], sizeof(int32_t) * (size_t)nx);
+            nx = dedup_sorted(xa, nx);
+            while (i < nq && jj < nx) {
+                if (qa[i] == xa[jj]) {
+                    cnt++;
+                    i++;
+                    jj++;
+                } else if (qa[i] < xa[jj]) {
+                    i++;
+                } else {
+                    jj++;
+                }
+            }
+            free(xa);
+            /* insert (x, cnt, nx) into the ordered list */
+            pos = m;
+            while (pos > 0) {
+                int better = sim_greater(measure, nq, cnt, nx, in[pos - 1], sz[pos - 1]);
+                int worse = sim_greater(measure, nq, in[pos - 1], sz[pos - 1], cnt, nx);
+                if (better || (!worse && x < ids[pos - 1])) pos--;
+                else break;
+            }
+            for (j = m; j > pos; j--) {
+                ids[j] = ids[j - 1];
+                in[j] = in[j - 1];
+                sz[j] = sz[j - 1];
+            }
+            ids[pos] = x;
+            in[pos] = cnt;
+            sz[pos] = nx;
+            m++;
+        }
+        for (j = 0; j < k; j++) {
+            out_ids[q * k + j] = j < m ? ids[j] : -1;
+            out_inter[q * k + j] = j < m ? in[j] : 0;
+        }
+        free(qa);
+        free(ids);
+        free(in);
+        free(sz);
+    }
+}
+
 int orc_num_threads(void)
 {
 #ifdef _OPENMP

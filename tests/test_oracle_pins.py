@@ -468,3 +468,80 @@ def test_recall_grows_with_tables(orc):
         rec.append(r)
     assert rec[0] <= rec[1] + 0.02 and rec[1] <= rec[2] + 0.02, rec
     assert rec[2] > rec[0], rec
+
+
+def _brute_rerank(measure, rows, qrows, cand, k):
+    """Candidates ranked by exact similarity with Python sets and fractions:
+    cosine (Eq. 3) is compared through its square, Jaccard directly."""
+    from fractions import Fraction
+    ids, inter = [], []
+    for q, cl in zip(qrows, cand):
+        a = set(q)
+        scored = []
+        for x in cl:
+            if x < 0:
+                continue
+            b = set(rows[x])
+            i = len(a & b)
+            if i == 0:
+                sim = Fraction(0)
+            elif measure == 0:
+                sim = Fraction(i * i, len(a) * len(b))
+            else:
+                sim = Fraction(i, len(a | b))
+            scored.append((-sim, x, i))
+        scored.sort()
+        row_i = [x for _, x, _ in scored][:k]
+        row_n = [i for _, _, i in scored][:k]
+        ids.append(row_i + [-1] * (k - len(row_i)))
+        inter.append(row_n + [0] * (k - len(row_n)))
+    return np.array(ids, dtype=np.int32), np.array(inter, dtype=np.int64)
+
+
+@pytest.mark.parametrize("measure", [0, 1])
+def test_rerank_brute_force(orc, measure):
+    # random small sets with duplicates and empty rows; candidates with
+    # repeats of -1; cosine and Jaccard orders differ on purpose (sizes vary)
+    rng = np.random.default_rng(41 + measure)
+    n, nq, nc, k = 60, 25, 12, 7
+    rows = [list(rng.integers(0, 40, size=int(rng.integers(0, 25)))) for _ in range(n)]
+    qrows = [list(rng.integers(0, 40, size=int(rng.integers(0, 25)))) for _ in range(nq)]
+    rows[3] = []
+    qrows[2] = []
+    cand = rng.integers(-1, n, size=(nq, nc)).astype(np.int32)
+    for q in range(nq):                      # candidate lists hold distinct ids
+        seen = set()
+        for c in range(nc):
+            if cand[q, c] in seen:
+                cand[q, c] = -1
+            seen.add(int(cand[q, c]))
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.array([c for r in rows for c in r], dtype=np.int32)
+    qrp = np.zeros(nq + 1, np.int64)
+    qrp[1:] = np.cumsum([len(r) for r in qrows])
+    qci = np.array([c for r in qrows for c in r], dtype=np.int32)
+    oi, on = orc.rerank(measure, rp, ci, qrp, qci, cand, k)
+    bi, bn = _brute_rerank(measure, rows, qrows, cand, k)
+    assert np.array_equal(oi, bi) and np.array_equal(on, bn)
+
+
+def test_rerank_cosine_and_jaccard_orders_differ(orc):
+    # query {0..9}; a = {0}: cosine 1/sqrt(10) = 0.316, Jaccard 1/10;
+    # b = {0, 1, 2} + 17 others: cosine 3/sqrt(200) = 0.212, Jaccard 3/27 = 0.111;
+    # c = {0..7} + 2 others: cosine 0.8, Jaccard 8/12
+    rows = [[0], [0, 1, 2] + list(range(100, 117)), list(range(8)) + [200, 201]]
+    rp = np.array([0, 1, 21, 31], np.int64)
+    ci = np.array([c for r in rows for c in r], dtype=np.int32)
+    qrp = np.array([0, 10], np.int64)
+    qci = np.arange(10, dtype=np.int32)
+    cand = np.array([[0, 1, 2]], dtype=np.int32)
+    oi, on = orc.rerank(0, rp, ci, qrp, qci, cand, 3)
+    assert oi.tolist() == [[2, 0, 1]] and on.tolist() == [[8, 1, 3]]
+    oi, on = orc.rerank(1, rp, ci, qrp, qci, cand, 3)
+    assert oi.tolist() == [[2, 1, 0]] and on.tolist() == [[8, 3, 1]]
+    # equal similarity: the smaller id first
+    rows2 = [list(range(4)), list(range(4))]
+    oi, _ = orc.rerank(0, np.array([0, 4, 8], np.int64), np.array(rows2[0] + rows2[1], np.int32),
+                       qrp, qci, np.array([[1, 0]], np.int32), 2)
+    assert oi.tolist() == [[0, 1]]
