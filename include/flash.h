@@ -198,6 +198,28 @@ FLASH_API int flash_knn_graph(const flash_params *p, int64_t n_rows, int64_t nnz
                               int32_t *out_counts, void *workspace, size_t workspace_bytes,
                               void *stream);
 
+#define FLASH_SIM_COSINE 0  /* Eq. 3: |x ∩ y| / sqrt(|x| |y|) */
+#define FLASH_SIM_JACCARD 1 /* Eq. 2's right-hand side: |x ∩ y| / |x ∪ y| */
+
+/* Exact re-rank (Sec. 4.3: the exact similarity is the accuracy gold
+ * standard; S@k averages it over the top k).  For each query row q of the
+ * CSR q_row_ptr / q_col_idx (n_queries rows, q_nnz columns) and its
+ * candidates cand_ids[q][0..n_cand) (ids of rows of the indexed CSR
+ * row_ptr / col_idx, n_indexed rows, nnz columns; ids < 0 or >= n_indexed
+ * are no candidate): the intersection |q ∩ x| is counted exactly, the
+ * candidates are ordered by `measure` (FLASH_SIM_*) descending, compared
+ * exactly in integers, ties by the smaller id, and the first k are written:
+ * out_ids[q][0..k) and out_inter[q][0..k) (int32), padded with (-1, 0).
+ * The similarity follows from the intersection and the two row lengths.
+ * Rows must hold distinct column ids (duplicates would be counted twice);
+ * order inside a row is free.  1 <= k <= n_cand <= 1024.  Needs no
+ * workspace. */
+FLASH_API int flash_rerank_exact(int measure, int64_t n_indexed, int64_t nnz, const int64_t *row_ptr,
+                                 const int32_t *col_idx, int64_t n_queries, int64_t q_nnz,
+                                 const int64_t *q_row_ptr, const int32_t *q_col_idx,
+                                 const int32_t *cand_ids, int32_t n_cand, int32_t k, int32_t *out_ids,
+                                 int32_t *out_inter, void *stream);
+
 /* Launch shapes (process-wide).  No field changes any result: they only
  * move the same work between launches, workgroups and waves.  A value of
  * 0 in a field marked "0 = ..." has that meaning; reserved must be 0. */

@@ -422,6 +422,24 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
+FLASH_API int flash_rerank_exact(int measure, int64_t n_indexed, int64_t nnz, const int64_t* row_ptr,
+                                 const int32_t* col_idx, int64_t n_queries, int64_t q_nnz,
+                                 const int64_t* q_row_ptr, const int32_t* q_col_idx, const int32_t* cand_ids,
+                                 int32_t n_cand, int32_t k, int32_t* out_ids, int32_t* out_inter, void* stream) {
+  if (measure != FLASH_SIM_COSINE && measure != FLASH_SIM_JACCARD)
+    return fail(FLASH_EINVAL, "measure must be FLASH_SIM_COSINE or FLASH_SIM_JACCARD");
+  if (n_indexed < 0 || n_queries < 0) return fail(FLASH_EINVAL, "sizes must be >= 0");
+  if (n_cand < 1 || n_cand > 1024) return fail(FLASH_EINVAL, "n_cand must be in [1, 1024]");
+  if (k < 1 || k > n_cand) return fail(FLASH_EINVAL, "k must be in [1, n_cand]");
+  int r;
+  if ((r = check_csr(n_indexed, nnz, row_ptr, col_idx))) return r;
+  if ((r = check_csr(n_queries, q_nnz, q_row_ptr, q_col_idx))) return r;
+  if (n_queries > 0 && (!cand_ids || !out_ids || !out_inter)) return fail(FLASH_EINVAL, "NULL array");
+  hipError_t e = launch_rerank(measure, n_indexed, nnz, row_ptr, col_idx, n_queries, q_nnz, q_row_ptr, q_col_idx,
+                               cand_ids, n_cand, k, out_ids, out_inter, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "rerank");
+}
+
 FLASH_API int flash_get_tuning(flash_tuning* out) {
   if (!out) return fail(FLASH_EINVAL, "out is NULL");
   *out = tuning_to_c(tuning());

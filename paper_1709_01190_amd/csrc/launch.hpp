@@ -69,6 +69,12 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
                         const int32_t* self_ids, int self_mode, int32_t k, const int32_t* k_per_query,
                         int32_t* out_ids, int32_t* out_counts, const QueryWs& w, hipStream_t s);
 
+// ---- exact re-rank (rerank.hip); measure 0 = cosine, 1 = Jaccard
+hipError_t launch_rerank(int measure, int64_t n_indexed, int64_t nnz, const int64_t* row_ptr,
+                         const int32_t* col_idx, int64_t n_queries, int64_t q_nnz, const int64_t* q_row_ptr,
+                         const int32_t* q_col_idx, const int32_t* cand, int32_t n_cand, int32_t k,
+                         int32_t* out_ids, int32_t* out_inter, hipStream_t s);
+
 // ---- misc
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 

@@ -91,6 +91,8 @@ def lib():
                             ctypes.c_size_t, _VP],
         "flash_insert_keys_append": [P, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_build_index_append": [P, _I64, _I64, _VP, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_rerank_exact": [ctypes.c_int, _I64, _I64, _VP, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32,
+                               ctypes.c_int32, _VP, _VP, _VP],
         "flash_get_tuning": [ctypes.POINTER(flash_tuning)],
         "flash_set_tuning": [ctypes.POINTER(flash_tuning)],
         "flash_autotune_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP,
@@ -273,6 +275,23 @@ def flash_query_batch_mixed(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_p
                                          _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
                                          _p(out_counts), _p(workspace),
                                          workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+SIM_COSINE, SIM_JACCARD = 0, 1
+
+
+def flash_rerank_exact(measure, row_ptr, col_idx, q_row_ptr, q_col_idx, cand_ids, k, out_ids, out_inter,
+                       stream=None):
+    """cand_ids: int32 [n_queries, n_cand]; out_ids / out_inter: int32 [n_queries * k]."""
+    n = row_ptr.numel() - 1
+    q = q_row_ptr.numel() - 1
+    nc = cand_ids.shape[-1] if cand_ids.dim() > 1 else cand_ids.numel() // max(q, 1)
+    _need(cand_ids, q * nc, (torch.int32,), "cand_ids")
+    _need(out_ids, q * k, (torch.int32,), "out_ids")
+    _need(out_inter, q * k, (torch.int32,), "out_inter")
+    _check(lib().flash_rerank_exact(int(measure), n, col_idx.numel(), _p(row_ptr), _p(col_idx) if col_idx.numel() else None,
+                                    q, q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx) if q_col_idx.numel() else None,
+                                    _p(cand_ids), nc, k, _p(out_ids), _p(out_inter), _s(stream)))
 
 
 def flash_get_tuning() -> flash_tuning:

@@ -678,3 +678,93 @@ def test_append_csr_batches_then_query(fl, orc):
     gi, gc = gpu_query(fl, p, counts, ids, spec.n_rows, okeys[sample], 20, sample.astype(np.int32))
     wi, wc = orc.query(op, ocounts, oids, okeys[sample], 20, self_ids=sample.astype(np.int32))
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+# ------------------------------------------------------------------ exact re-rank
+
+def _gpu_rerank(fl, measure, rp, ci, qrp, qci, cand, k):
+    import torch
+    q, nc = cand.shape
+    oi = torch.empty(q * k, dtype=torch.int32, device="cuda")
+    on = torch.empty(q * k, dtype=torch.int32, device="cuda")
+    fl.flash_rerank_exact(measure, dev(rp), dev(ci), dev(qrp), dev(qci), dev(cand), k, oi, on)
+    torch.cuda.synchronize()
+    return i32(oi).reshape(q, k), i32(on).reshape(q, k)
+
+
+def _random_rows(rng, n, max_len, n_cols):
+    rows = [np.unique(rng.integers(0, n_cols, size=int(rng.integers(0, max_len + 1)))) for _ in range(n)]
+    rp = np.zeros(n + 1, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32) if rp[-1] else np.zeros(0, np.int32)
+    return rp, ci
+
+
+@pytest.mark.parametrize("measure", [0, 1])
+def test_rerank_random_rows(fl, orc, measure):
+    say("rerank random measure", measure)
+    rng = np.random.default_rng(50 + measure)
+    rp, ci = _random_rows(rng, 2000, 60, 300)
+    qrp, qci = _random_rows(rng, 700, 60, 300)
+    for nc, k in ((1, 1), (37, 7), (200, 200), (1024, 16)):
+        cand = rng.integers(-1, 2000, size=(700, nc)).astype(np.int32)
+        for q in range(700):                   # distinct ids per list
+            _, first = np.unique(cand[q], return_index=True)
+            dup = np.ones(nc, bool)
+            dup[first] = False
+            cand[q, dup] = -1
+        wi, wn = orc.rerank(measure, rp, ci, qrp, qci, cand, k)
+        gi, gn = _gpu_rerank(fl, measure, rp, ci, qrp, qci, cand, k)
+        assert np.array_equal(gi, wi) and np.array_equal(gn, wn), (nc, k)
+        # ids past the index are no candidate
+        bad = cand.copy()
+        bad[:, 0] = 2000 + 5
+        ref = cand.copy()
+        ref[:, 0] = -1
+        wi, wn = orc.rerank(measure, rp, ci, qrp, qci, ref, k)
+        gi, gn = _gpu_rerank(fl, measure, rp, ci, qrp, qci, bad, k)
+        assert np.array_equal(gi, wi) and np.array_equal(gn, wn), (nc, k, "out of range")
+
+
+def test_rerank_long_rows_and_top_column(fl, orc):
+    # queries longer than one LDS round (4,096 columns), and column 0xFFFFFFFF
+    say("rerank long rows")
+    rng = np.random.default_rng(60)
+    rows = [np.unique(rng.integers(0, 30000, size=int(s))) for s in rng.integers(1000, 12000, size=300)]
+    rows[5] = np.concatenate([rows[5], [-1]])          # read as column 0xFFFFFFFF
+    qrows = [np.unique(np.concatenate([rows[i][: len(rows[i]) // 2], rng.integers(0, 30000, size=3000)]))
+             for i in range(0, 300, 7)]
+    qrows[0] = np.concatenate([qrows[0], [-1]])
+    rp = np.zeros(301, np.int64)
+    rp[1:] = np.cumsum([len(r) for r in rows])
+    ci = np.concatenate(rows).astype(np.int32)
+    nq = len(qrows)
+    qrp = np.zeros(nq + 1, np.int64)
+    qrp[1:] = np.cumsum([len(r) for r in qrows])
+    qci = np.concatenate(qrows).astype(np.int32)
+    cand = np.array([rng.permutation(300)[:64] for _ in range(nq)], dtype=np.int32)
+    cand[0, 0] = 5
+    cand[0, 1:] = np.where(cand[0, 1:] == 5, 6, cand[0, 1:])
+    for measure in (0, 1):
+        wi, wn = orc.rerank(measure, rp, ci, qrp, qci, cand, 20)
+        gi, gn = _gpu_rerank(fl, measure, rp, ci, qrp, qci, cand, 20)
+        assert np.array_equal(gi, wi) and np.array_equal(gn, wn), measure
+
+
+def test_rerank_of_flash_candidates(fl, orc):
+    # the use it is for: FLASH's count-ranked top-100 of URL-shaped queries
+    # (the oracle's lists, so no input comes from the GPU) re-ranked by
+    # exact cosine to a top-10
+    import dataclasses
+    from paper_1709_01190_amd import datagen
+    say("rerank flash candidates")
+    spec = datagen.scaled(datagen.URL, 60_000)
+    rp, ci = (a.numpy() for a in datagen.make_rows(spec, 1))
+    qrp, qci = (a.numpy() for a in datagen.make_rows(dataclasses.replace(spec, n_rows=1500), 1, row_seed=2))
+    op = orc.params(5, 32, 3, 64, seed=1)
+    counts, ids = orc.build_tables(op, orc.doph(op, rp, ci))
+    cand, _ = orc.query(op, counts, ids, orc.doph(op, qrp, qci), 100)
+    for measure in (0, 1):
+        wi, wn = orc.rerank(measure, rp, ci, qrp, qci, cand, 10)
+        gi, gn = _gpu_rerank(fl, measure, rp, ci, qrp, qci, cand, 10)
+        assert np.array_equal(gi, wi) and np.array_equal(gn, wn), measure

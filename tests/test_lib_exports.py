@@ -135,3 +135,11 @@ def test_append_arguments_are_checked_on_the_host(fl):
     # nothing to add: nothing enqueued, no workspace needed
     assert L.flash_insert_keys_append(ctypes.byref(p), 0, None, 5, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                       None, 0, None) == fl.FLASH_OK
+
+
+def test_rerank_arguments_are_checked_on_the_host(fl):
+    L = fl.lib()
+    vp = ctypes.c_void_p(16)
+    for measure, nc, k in ((2, 10, 5), (0, 0, 1), (0, 1025, 5), (1, 10, 11), (1, 10, 0)):
+        r = L.flash_rerank_exact(measure, 10, 100, vp, vp, 5, 50, vp, vp, vp, nc, k, vp, vp, None)
+        assert r == fl.FLASH_EINVAL, (measure, nc, k)
