@@ -11,6 +11,8 @@ What each function follows (arXiv 1709.01190):
   jaccard_knn     Eq. 2 right-hand side (exact Jaccard), for recall
   rerank          Sec. 4.3 gold standard: exact cosine (Eq. 3) or Jaccard
                   ordering of candidate lists
+  pool_size,      Sec. 3.5 reservoir sharing (a seeded random map of buckets
+  reservoir       to a pool of about F * L * M reservoirs)
 """
 from __future__ import annotations
 
@@ -30,7 +32,7 @@ class Params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("bits_per_hash", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("densify_attempts", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("share_permille", ctypes.c_int32)]
 
 
 def build(force: bool = True) -> str:
@@ -72,6 +74,12 @@ def lib():
         L.orc_jaccard_knn.restype = None
         L.orc_jaccard_knn.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                       P, ctypes.c_int32, P, P, P]
+        L.orc_pool_size.restype = ctypes.c_uint64
+        L.orc_pool_size.argtypes = [P]
+        L.orc_reservoir.restype = ctypes.c_uint64
+        L.orc_reservoir.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64]
+        L.orc_share_seed.restype = ctypes.c_uint32
+        L.orc_share_seed.argtypes = [ctypes.c_uint64]
         L.orc_rerank.restype = None
         L.orc_rerank.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int32,
                                  ctypes.c_int32, P, P]
@@ -84,8 +92,22 @@ def _ptr(a):
     return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
 
 
-def params(K, L, bits_per_hash, R, seed=1, densify_attempts=64) -> Params:
-    return Params(K, L, bits_per_hash, R, seed, densify_attempts, 0)
+def params(K, L, bits_per_hash, R, seed=1, densify_attempts=64, share_permille=0) -> Params:
+    return Params(K, L, bits_per_hash, R, seed, densify_attempts, share_permille)
+
+
+def pool_size(p: Params) -> int:
+    """Reservoirs in the index: L * M, or about F * L * M when shared (Sec. 3.5)."""
+    return lib().orc_pool_size(ctypes.byref(p))
+
+
+def reservoir(p: Params, t: int, m: int) -> int:
+    """Reservoir of bucket m of table t."""
+    return lib().orc_reservoir(ctypes.byref(p), t, m)
+
+
+def share_seed(seed: int) -> int:
+    return lib().orc_share_seed(seed)
 
 
 def seeds(seed: int):
@@ -126,12 +148,18 @@ def doph(p: Params, row_ptr, col_idx, want_codes=False):
 
 
 def build_tables(p: Params, keys):
-    """Returns counts uint32 [L][M] and ids int32 [L][M][R] (-1 past occupancy)."""
+    """Returns counts uint32 [L][M] and ids int32 [L][M][R] (-1 past
+    occupancy); with shared reservoirs counts [P] and ids [P][R]."""
     keys = np.ascontiguousarray(keys, dtype=np.uint32)
     n = keys.shape[0]
     M = 1 << (p.K * p.bits_per_hash)
-    counts = np.empty((p.L, M), dtype=np.uint32)
-    ids = np.empty((p.L, M, p.R), dtype=np.int32)
+    if 0 < p.share_permille < 1000:
+        P = pool_size(p)
+        counts = np.empty(P, dtype=np.uint32)
+        ids = np.empty((P, p.R), dtype=np.int32)
+    else:
+        counts = np.empty((p.L, M), dtype=np.uint32)
+        ids = np.empty((p.L, M, p.R), dtype=np.int32)
     lib().orc_build(ctypes.byref(p), n, _ptr(keys), _ptr(counts), _ptr(ids))
     return counts, ids
 

@@ -27,6 +27,13 @@
  *   orc_jaccard_knn                    exact Jaccard neighbours (Eq. 2's right
  *                                      side) for recall; pinned by direct set
  *                                      intersection on tiny inputs.
+ *   orc_pool_size, orc_reservoir       Sec. 3.5 reservoir sharing; pinned by
+ *                                      F = 1 giving the plain index, the
+ *                                      rounding of F * L * M, a uniform map,
+ *                                      brute-force shared tables and queries.
+ *   orc_rerank                         Sec. 4.3 exact cosine (Eq. 3) / Jaccard
+ *                                      ordering; pinned by Python sets and
+ *                                      fractions and a hand-worked case.
  */
 #include <stdint.h>
 #include <stdlib.h>
@@ -44,7 +51,7 @@ typedef struct {
     int32_t R;                /* reservoir size (Sec. 2.4, Alg. 2) */
     uint64_t seed;            /* user seed */
     int32_t densify_attempts; /* random probes per empty bin before rotation */
-    int32_t reserved;
+    int32_t share_permille;   /* reservoir sharing F in thousandths (Sec. 3.5); 0 or 1000: none */
 } orc_params;
 
 /* ---- bit-level building blocks ------------------------------------------ */
@@ -80,6 +87,13 @@ void orc_seeds(uint64_t seed, uint32_t *s_h, uint32_t *s_d, uint64_t *s_p)
     *s_d = (uint32_t)orc_mix64(state);
     state += 0x9E3779B97F4A7C15ULL;
     *s_p = orc_mix64(state);
+}
+
+/* The fourth output of the same splitmix64 sequence: the seed of the
+ * bucket-to-reservoir map used when reservoirs are shared (Sec. 3.5). */
+uint32_t orc_share_seed(uint64_t seed)
+{
+    return (uint32_t)orc_mix64(seed + 4 * 0x9E3779B97F4A7C15ULL);
 }
 
 /* Position of 32-bit value h in a range of n equal slices (multiply-shift). */
@@ -210,12 +224,53 @@ static int cmp_arrival(const void *a, const void *b)
     return 0;
 }
 
+/* ---- Sec. 3.5: reservoir sharing ----------------------------------------- */
+
+static int shared(const orc_params *p)
+{
+    return p->share_permille > 0 && p->share_permille < 1000;
+}
+
+/*
+ * Number of reservoirs.  Without sharing, one per bucket: L * M.  With
+ * sharing, "allocated range = F * actual range": ceil(F * L * M) with F =
+ * share_permille / 1000, rounded up to a multiple of 16384 (or, below that,
+ * to a power of two).
+ */
+uint64_t orc_pool_size(const orc_params *p)
+{
+    const uint64_t M = 1ULL << (p->K * p->bits_per_hash);
+    const uint64_t LM = (uint64_t)p->L * M;
+    uint64_t P, unit = 1;
+    if (!shared(p)) return LM;
+    P = (LM * (uint64_t)p->share_permille + 999) / 1000;
+    if (P < 1) P = 1;
+    while (unit < P && unit < 16384) unit <<= 1;
+    return (P + unit - 1) / unit * unit;
+}
+
+/*
+ * Reservoir of bucket m of table t.  Without sharing: t * M + m.  With
+ * sharing, every bucket is given one reservoir of the pool at random (a
+ * seeded hash of its index), so buckets of any tables may share one.
+ */
+uint64_t orc_reservoir(const orc_params *p, uint64_t t, uint64_t m)
+{
+    const uint64_t M = 1ULL << (p->K * p->bits_per_hash);
+    if (!shared(p)) return t * M + m;
+    return slice_of(orc_fmix32((uint32_t)(t * M + m) ^ orc_share_seed(p->seed)),
+                    (uint32_t)orc_pool_size(p));
+}
+
 /*
  * counts[t][m] = number of rows whose key in table t is m (Alg. 2's
  * ReservoirCounter after all additions); ids[t][m][0 .. min(count, R)) hold
  * the ids of the smallest priorities in ascending priority order; the other
  * slots are -1.  Rows whose key is ORC_EMPTY or >= 2^(K*b) are not added.
  */
+static void build_shared(const orc_params *p, int64_t n_rows, const uint32_t *keys,
+                         uint32_t *counts, int32_t *ids);
+
 void orc_build(const orc_params *p, int64_t n_rows, const uint32_t *keys,
                uint32_t *counts, int32_t *ids)
 {
@@ -224,6 +279,10 @@ void orc_build(const orc_params *p, int64_t n_rows, const uint32_t *keys,
     uint32_t s_h, s_d;
     uint64_t s_p;
     int t;
+    if (shared(p)) {
+        build_shared(p, n_rows, keys, counts, ids);
+        return;
+    }
     orc_seeds(p->seed, &s_h, &s_d, &s_p);
 #pragma omp parallel for schedule(dynamic, 1)
     for (t = 0; t < L; t++) {
@@ -252,6 +311,65 @@ void orc_build(const orc_params *p, int64_t n_rows, const uint32_t *keys,
         }
         free(arr);
     }
+}
+
+/*
+ * The same bottom-R reading over a shared pool: every (table, row) arrival
+ * goes to the reservoir of its bucket; a reservoir counts all its arrivals
+ * and keeps the R with the smallest priority, where the priority of id i in
+ * reservoir r is orc_priority(s_p, r, i) (the reservoir takes the place of
+ * the table).  An id that reaches one reservoir from two tables arrives
+ * twice, with the same priority.
+ */
+static void build_shared(const orc_params *p, int64_t n_rows, const uint32_t *keys,
+                         uint32_t *counts, int32_t *ids)
+{
+    const int L = p->L, R = p->R;
+    const uint64_t M = 1ULL << (p->K * p->bits_per_hash);
+    const uint64_t P = orc_pool_size(p);
+    uint32_t s_h, s_d;
+    uint64_t s_p;
+    arrival *arr = (arrival *)malloc(sizeof(arrival) * (size_t)(n_rows * L + 1));
+    uint64_t *res = (uint64_t *)malloc(sizeof(uint64_t) * (size_t)(n_rows * L + 1));
+    int64_t n = 0, i, g;
+    uint64_t r;
+    orc_seeds(p->seed, &s_h, &s_d, &s_p);
+    memset(counts, 0, sizeof(uint32_t) * P);
+    for (r = 0; r < P * (uint64_t)R; r++) ids[r] = -1;
+    for (i = 0; i < n_rows; i++) {
+        int t;
+        for (t = 0; t < L; t++) {
+            uint32_t k = keys[i * L + t];
+            if (k == ORC_EMPTY || (uint64_t)k >= M) continue;
+            res[n] = orc_reservoir(p, (uint64_t)t, k);
+            n++;
+        }
+    }
+    /* arrivals keyed by (reservoir, priority); the reservoir index fits in
+     * the 32-bit key field because P <= L * M < 2^32 */
+    n = 0;
+    for (i = 0; i < n_rows; i++) {
+        int t;
+        for (t = 0; t < L; t++) {
+            uint32_t k = keys[i * L + t];
+            if (k == ORC_EMPTY || (uint64_t)k >= M) continue;
+            arr[n].key = (uint32_t)res[n];
+            arr[n].pri = orc_priority(s_p, (int)res[n], (int32_t)i);
+            n++;
+        }
+    }
+    qsort(arr, (size_t)n, sizeof(arrival), cmp_arrival);
+    for (g = 0; g < n;) {
+        int64_t e = g;
+        uint32_t k = arr[g].key;
+        while (e < n && arr[e].key == k) e++;
+        counts[k] = (uint32_t)(e - g);
+        for (i = g; i < e && i - g < R; i++)
+            ids[(uint64_t)k * R + (uint64_t)(i - g)] = (int32_t)(uint32_t)(arr[i].pri & 0xFFFFFFFFu);
+        g = e;
+    }
+    free(arr);
+    free(res);
 }
 
 /* ---- Alg. 3: gather L reservoirs, count, rank --------------------------- */
@@ -300,11 +418,13 @@ void orc_query(const orc_params *p, const uint32_t *counts, const int32_t *ids,
             for (t = 0; t < L; t++) {
                 uint32_t key = qkeys[q * L + t];
                 uint64_t occ;
+                uint64_t res;
                 if (key == ORC_EMPTY || (uint64_t)key >= M) continue;
-                occ = counts[(uint64_t)t * M + key];
+                res = orc_reservoir(p, (uint64_t)t, key);
+                occ = counts[res];
                 if (occ > (uint64_t)R) occ = (uint64_t)R;
                 for (j = 0; j < (int)occ; j++) {
-                    int32_t x = ids[((uint64_t)t * M + key) * (uint64_t)R + (uint64_t)j];
+                    int32_t x = ids[res * (uint64_t)R + (uint64_t)j];
                     if (self >= 0 && x == self) continue;
                     A[na++] = x;
                 }

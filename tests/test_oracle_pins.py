@@ -545,3 +545,113 @@ def test_rerank_cosine_and_jaccard_orders_differ(orc):
     oi, _ = orc.rerank(0, np.array([0, 4, 8], np.int64), np.array(rows2[0] + rows2[1], np.int32),
                        qrp, qci, np.array([[1, 0]], np.int32), 2)
     assert oi.tolist() == [[0, 1]]
+
+
+# ---- reservoir sharing (Sec. 3.5) ---------------------------------------------
+
+def test_sharing_off_is_the_plain_index(orc):
+    # F = 1 (share_permille 0 or 1000) is the unshared index, reservoir = t * M + m
+    rng = np.random.default_rng(70)
+    K, L, b, R = 2, 4, 3, 5
+    M = 1 << (K * b)
+    keys = rng.integers(0, M, size=(500, L), dtype=np.int64).astype(np.uint32)
+    c0, i0 = orc.build_tables(orc.params(K, L, b, R, seed=3), keys)
+    for permille in (0, 1000):
+        p = orc.params(K, L, b, R, seed=3, share_permille=permille)
+        assert orc.pool_size(p) == L * M
+        assert orc.reservoir(p, 2, 17) == 2 * M + 17
+        c1, i1 = orc.build_tables(p, keys)
+        assert np.array_equal(c0, c1) and np.array_equal(i0, i1)
+
+
+def test_pool_size_is_f_times_range_rounded(orc):
+    # allocated range = F * actual range, rounded up to a multiple of 16384
+    # (or, below that, to a power of two)
+    for K, L, b, permille in ((4, 64, 4, 200), (5, 32, 3, 500), (1, 2, 2, 500), (2, 3, 3, 1),
+                              (4, 16, 4, 999), (3, 5, 2, 333)):
+        LM = L << (K * b)
+        P = -(-LM * permille // 1000)
+        unit = 1
+        while unit < P and unit < 16384:
+            unit *= 2
+        want = -(-P // unit) * unit
+        assert orc.pool_size(orc.params(K, L, b, 8, share_permille=permille)) == want
+
+
+def test_reservoir_map_is_uniform_and_seeded(orc):
+    K, L, b = 3, 8, 3
+    M = 1 << (K * b)
+    p = orc.params(K, L, b, 8, seed=5, share_permille=250)
+    P = orc.pool_size(p)
+    res = np.array([[orc.reservoir(p, t, m) for m in range(M)] for t in range(L)])
+    assert res.min() >= 0 and res.max() < P
+    hist = np.bincount(res.ravel(), minlength=P)
+    exp = L * M / P
+    chi2 = ((hist - exp) ** 2 / exp).sum()
+    assert chi2 < P + 6 * math.sqrt(2 * P)          # P - 1 degrees of freedom
+    q = orc.params(K, L, b, 8, seed=6, share_permille=250)
+    other = np.array([[orc.reservoir(q, t, m) for m in range(M)] for t in range(L)])
+    assert (other != res).mean() > 0.9                # another seed, another map
+
+
+@pytest.mark.parametrize("permille", [1, 100, 600])
+def test_shared_tables_brute_force(orc, permille):
+    # a reservoir counts every (table, row) arrival of the buckets mapped to
+    # it and keeps the R smallest priorities pk(reservoir, id); a row can
+    # arrive twice (from two tables) when the pool is small
+    rng = np.random.default_rng(71 + permille)
+    K, L, b, R = 2, 3, 3, 4
+    M = 1 << (K * b)
+    n = 400
+    keys = rng.integers(0, M, size=(n, L), dtype=np.int64).astype(np.uint32)
+    keys[rng.random((n, L)) < 0.05] = EMPTY
+    p = orc.params(K, L, b, R, seed=12, share_permille=permille)
+    P = orc.pool_size(p)
+    counts, ids = orc.build_tables(p, keys)
+    assert counts.shape == (P,) and ids.shape == (P, R)
+    s_p = orc.seeds(12)[2]
+    arrivals = collections.defaultdict(list)
+    for i in range(n):
+        for t in range(L):
+            if keys[i, t] != EMPTY:
+                arrivals[orc.reservoir(p, t, int(keys[i, t]))].append(i)
+    twice = 0
+    for r in range(P):
+        arr = arrivals.get(r, [])
+        twice += len(arr) - len(set(arr))
+        assert counts[r] == len(arr)
+        pri = sorted((orc.priority(s_p, r, i), i) for i in arr)
+        occ = min(len(arr), R)
+        assert list(ids[r, :occ]) == [i for _, i in pri[:R]]
+        assert np.all(ids[r, occ:] == -1)
+    if permille == 1:
+        assert twice > 0
+
+
+@pytest.mark.parametrize("permille", [50, 400])
+def test_shared_query_brute_force(orc, permille):
+    # a query aggregates the reservoirs of its L buckets (a reservoir reached
+    # from two tables is aggregated twice) and counts occurrences
+    rng = np.random.default_rng(80 + permille)
+    K, L, b, R, k = 2, 6, 3, 5, 9
+    M = 1 << (K * b)
+    keys = rng.integers(0, M, size=(300, L), dtype=np.int64).astype(np.uint32)
+    p = orc.params(K, L, b, R, seed=4, share_permille=permille)
+    counts, ids = orc.build_tables(p, keys)
+    qkeys = keys[:50].copy()
+    qkeys[3] = EMPTY
+    self_ids = np.arange(50, dtype=np.int32)
+    oi, oc = orc.query(p, counts, ids, qkeys, k, self_ids=self_ids)
+    for qi in range(50):
+        c = collections.Counter()
+        for t in range(L):
+            m = int(qkeys[qi, t])
+            if m == EMPTY:
+                continue
+            r = orc.reservoir(p, t, m)
+            for x in ids[r, :min(int(counts[r]), R)]:
+                if x != self_ids[qi]:
+                    c[int(x)] += 1
+        want = sorted(c.items(), key=lambda kv: (-kv[1], kv[0]))[:k]
+        want += [(-1, 0)] * (k - len(want))
+        assert list(zip(oi[qi].tolist(), oc[qi].tolist())) == want
