@@ -315,11 +315,12 @@ void orc_build(const orc_params *p, int64_t n_rows, const uint32_t *keys,
 
 /*
  * The same bottom-R reading over a shared pool: every (table, row) arrival
- * goes to the reservoir of its bucket; a reservoir counts all its arrivals
- * and keeps the R with the smallest priority, where the priority of id i in
+ * goes to the reservoir of its bucket; a reservoir counts its arrivals and
+ * keeps the R with the smallest priority, where the priority of id i in
  * reservoir r is orc_priority(s_p, r, i) (the reservoir takes the place of
- * the table).  An id that reaches one reservoir from two tables arrives
- * twice, with the same priority.
+ * the table).  A row whose buckets in several tables map to one reservoir
+ * arrives there once (from its first such table), so a reservoir holds
+ * distinct ids and a query's count stays at most L.
  */
 static void build_shared(const orc_params *p, int64_t n_rows, const uint32_t *keys,
                          uint32_t *counts, int32_t *ids)
@@ -336,25 +337,23 @@ static void build_shared(const orc_params *p, int64_t n_rows, const uint32_t *ke
     orc_seeds(p->seed, &s_h, &s_d, &s_p);
     memset(counts, 0, sizeof(uint32_t) * P);
     for (r = 0; r < P * (uint64_t)R; r++) ids[r] = -1;
-    for (i = 0; i < n_rows; i++) {
-        int t;
-        for (t = 0; t < L; t++) {
-            uint32_t k = keys[i * L + t];
-            if (k == ORC_EMPTY || (uint64_t)k >= M) continue;
-            res[n] = orc_reservoir(p, (uint64_t)t, k);
-            n++;
-        }
-    }
     /* arrivals keyed by (reservoir, priority); the reservoir index fits in
-     * the 32-bit key field because P <= L * M < 2^32 */
-    n = 0;
+     * the 32-bit key field because P < 2^32 */
     for (i = 0; i < n_rows; i++) {
-        int t;
+        int t, u;
+        int64_t first = n;
         for (t = 0; t < L; t++) {
             uint32_t k = keys[i * L + t];
+            uint64_t r;
+            int seen = 0;
             if (k == ORC_EMPTY || (uint64_t)k >= M) continue;
-            arr[n].key = (uint32_t)res[n];
-            arr[n].pri = orc_priority(s_p, (int)res[n], (int32_t)i);
+            r = orc_reservoir(p, (uint64_t)t, k);
+            for (u = (int)first; u < (int)n; u++)
+                if (res[u] == r) seen = 1;
+            if (seen) continue;
+            res[n] = r;
+            arr[n].key = (uint32_t)r;
+            arr[n].pri = orc_priority(s_p, (int)r, (int32_t)i);
             n++;
         }
     }
