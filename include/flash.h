@@ -33,7 +33,8 @@
  *    the number of rows whose key in table t is m; slots
  *    [0, min(counts[t][m], R)) of ids[t][m] hold the kept row ids in
  *    ascending reservoir priority; later slots are not part of the index and
- *    are never read.
+ *    are never read.  With shared reservoirs (flash_params.share_permille)
+ *    the arrays are counts uint32[P] and ids int32[P][R] over the pool.
  */
 #ifndef FLASH_H
 #define FLASH_H
@@ -60,10 +61,22 @@ extern "C" {
 /* Key of an empty row or query in every table (never inserted). */
 #define FLASH_EMPTY_KEY 0xFFFFFFFFu
 
-/* Method parameters (Sec. 2.2, Sec. 4.4.1).  Limits checked by every call:
- * 1 <= K, 1 <= L <= 256, 1 <= bits_per_hash, K * bits_per_hash <= 30,
- * K * L <= 4096 (DOPH bins), 1 <= R <= 1024, L * R <= 8192, L * 2^(K * b) < 2^32,
- * 0 <= densify_attempts <= 65535, reserved == 0. */
+/* Method parameters (Sec. 2.2, Sec. 4.4.1, Sec. 3.5).  Limits checked by
+ * every call: 1 <= K, 1 <= L <= 256, 1 <= bits_per_hash, K * bits_per_hash
+ * <= 30, K * L <= 4096 (DOPH bins), 1 <= R <= 1024, L * R <= 8192,
+ * L * 2^(K * b) < 2^32, 0 <= densify_attempts <= 65535,
+ * 0 <= share_permille <= 1000.
+ *
+ * Reservoir sharing (Sec. 3.5, "allocated range = F * actual range"): with
+ * 0 < share_permille < 1000, F = share_permille / 1000 and the index has
+ * P = ceil(F * L * M) reservoirs, rounded up to a multiple of 16384 (or,
+ * below that, to a power of two); bucket m of table t uses reservoir
+ * floor(fmix32((t * M + m) ^ s_r) * P / 2^32), a seeded random map (s_r:
+ * the fourth splitmix64 output of `seed`), so buckets of any tables may share
+ * one.  A reservoir keeps its R lowest-priority arrivals, with priorities
+ * keyed by the reservoir instead of the table; a query aggregates the
+ * reservoirs of its L buckets and counts occurrences.  0 or 1000: no
+ * sharing, P = L * M and reservoir t * M + m. */
 typedef struct flash_params {
     int32_t K;                /* minhashes per table key (meta-hash width)      */
     int32_t L;                /* number of hash tables                          */
@@ -72,7 +85,7 @@ typedef struct flash_params {
     uint64_t seed;            /* expands to the permutation, densification and
                                  reservoir-priority seeds                       */
     int32_t densify_attempts; /* random probes per empty DOPH bin (default 64)  */
-    int32_t reserved;         /* must be 0                                      */
+    int32_t share_permille;   /* reservoir sharing F in thousandths; 0: none    */
 } flash_params;
 
 /* Workspace users, for flash_workspace_bytes(). */
@@ -87,8 +100,8 @@ typedef struct flash_params {
  * FLASH_ENOTIMPL with a message in flash_last_error(). */
 FLASH_API int flash_check_params(const flash_params *p);
 
-/* Host only.  Element counts of the two index arrays: counts (L * M) and
- * ids (L * M * R). */
+/* Host only.  Element counts of the two index arrays: counts (P) and ids
+ * (P * R), P = L * M without reservoir sharing. */
 FLASH_API int flash_index_elems(const flash_params *p, uint64_t *counts_elems,
                                 uint64_t *ids_elems);
 

@@ -47,6 +47,9 @@ struct QueryArgs {
   int r_aligned;              // R % 4 == 0: a task is one 16-byte load
   uint32_t max_total;         // candidates this launch's table accepts
   uint32_t sb;                // survivor buffer entries
+  int shared;                 // reservoirs shared through the seeded map
+  uint32_t s_r;
+  uint64_t P;                 // reservoirs in the index
 };
 
 __host__ __device__ inline uint32_t slack_for(uint32_t need) { return need / 8 > 16 ? need / 8 : 16; }
@@ -328,7 +331,7 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
       if (t < L) {
         const uint32_t key = a.qkeys[q * (uint64_t)L + t];
         if (key < a.M) {
-          const uint64_t bucket = (uint64_t)t * a.M + key;
+          const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, key);
           const uint32_t cnt = a.counts[bucket];
           nt = cnt < R ? cnt : R;
           base = bucket * R;
@@ -611,7 +614,7 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
       if (t < L) {
         const uint32_t key = a.qkeys[q * (uint64_t)L + t];
         if (key < a.M) {
-          const uint64_t bucket = (uint64_t)t * a.M + key;
+          const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, key);
           const uint32_t cnt = a.counts[bucket];
           nt = cnt < R ? cnt : R;
           base = bucket * R;
@@ -961,6 +964,9 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   a.L = c.L;
   a.R = c.R;
   a.k = k;
+  a.shared = c.shared ? 1 : 0;
+  a.s_r = c.s_r;
+  a.P = c.P;
   a.self_mode = self_mode;
   a.k_per_query = k_per_query;
   a.cbits = 32 - __builtin_clz((unsigned)c.L + 1u);

@@ -25,7 +25,8 @@ int hip_fail(hipError_t e, const char* where) {
 
 int make_cfg(const flash_params* p, Cfg* c) {
   if (!p) return fail(FLASH_EINVAL, "params is NULL");
-  if (p->reserved != 0) return fail(FLASH_EINVAL, "params.reserved must be 0");
+  if (p->share_permille < 0 || p->share_permille > 1000)
+    return fail(FLASH_EINVAL, "share_permille must be in [0, 1000]");
   if (p->K < 1 || p->L < 1 || p->bits_per_hash < 1 || p->R < 1)
     return fail(FLASH_EINVAL, "K, L, bits_per_hash and R must be >= 1");
   if (p->L > 256) return fail(FLASH_ENOTIMPL, "L > 256 is not supported");
@@ -47,6 +48,17 @@ int make_cfg(const flash_params* p, Cfg* c) {
   c->M = 1u << (p->K * p->bits_per_hash);
   c->mask = (1u << p->bits_per_hash) - 1u;
   c->seeds = expand_seed(p->seed);
+  c->s_r = c->seeds.s_r;
+  const uint64_t LM = (uint64_t)c->L * c->M;
+  c->shared = p->share_permille > 0 && p->share_permille < 1000;
+  c->P = LM;
+  if (c->shared) {
+    // ceil(F * L * M), rounded up to a multiple of 16384 (or a power of two below that)
+    uint64_t P = (LM * (uint64_t)p->share_permille + 999) / 1000, unit = 1;
+    if (P < 1) P = 1;
+    while (unit < P && unit < 16384) unit <<= 1;
+    c->P = (P + unit - 1) / unit * unit;
+  }
   return FLASH_OK;
 }
 
@@ -161,8 +173,8 @@ FLASH_API int flash_index_elems(const flash_params* p, uint64_t* counts_elems, u
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
-  if (counts_elems) *counts_elems = (uint64_t)c.L * c.M;
-  if (ids_elems) *ids_elems = (uint64_t)c.L * c.M * (uint64_t)c.R;
+  if (counts_elems) *counts_elems = c.P;
+  if (ids_elems) *ids_elems = c.P * (uint64_t)c.R;
   return FLASH_OK;
 }
 

@@ -20,6 +20,16 @@ __device__ __forceinline__ uint32_t fmix32(uint32_t h) {
   return h;
 }
 
+// The same finaliser, callable on the host too.
+__host__ __device__ __forceinline__ uint32_t fmix32_hd(uint32_t h) {
+  h ^= h >> 16;
+  h *= 0x85EBCA6Bu;
+  h ^= h >> 13;
+  h *= 0xC2B2AE35u;
+  h ^= h >> 16;
+  return h;
+}
+
 // splitmix64 output function: seed expansion and reservoir priorities.
 __host__ __device__ __forceinline__ uint64_t splitmix_out(uint64_t z) {
   z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
@@ -31,9 +41,10 @@ struct Seeds {
   uint32_t s_h;  // column permutation
   uint32_t s_d;  // densification probes
   uint64_t s_p;  // reservoir priorities
+  uint32_t s_r;  // bucket -> shared reservoir map
 };
 
-// One user seed -> three seeds: the first three outputs of the splitmix64
+// One user seed -> four seeds: the first four outputs of the splitmix64
 // sequence started at `seed`.
 inline Seeds expand_seed(uint64_t seed) {
   const uint64_t g = 0x9E3779B97F4A7C15ull;
@@ -41,6 +52,7 @@ inline Seeds expand_seed(uint64_t seed) {
   s.s_h = (uint32_t)splitmix_out(seed + g);
   s.s_d = (uint32_t)splitmix_out(seed + 2 * g);
   s.s_p = splitmix_out(seed + 3 * g);
+  s.s_r = (uint32_t)splitmix_out(seed + 4 * g);
   return s;
 }
 

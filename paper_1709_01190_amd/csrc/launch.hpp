@@ -14,7 +14,17 @@ struct Cfg {
   uint32_t M;      // buckets per table, 2^(K*b)
   uint32_t mask;   // 2^b - 1
   Seeds seeds;
+  bool shared;     // reservoirs shared through a seeded map (Sec. 3.5)
+  uint32_t s_r;    // seed of that map
+  uint64_t P;      // reservoirs: L * M, or the shared pool
 };
+
+// Reservoir of bucket m of table t (see flash.h, flash_params).
+__host__ __device__ __forceinline__ uint64_t reservoir_of(bool shared, uint32_t s_r, uint64_t P, uint32_t M,
+                                                          uint32_t t, uint32_t m) {
+  if (!shared) return (uint64_t)t * M + m;
+  return ((uint64_t)fmix32_hd(((uint32_t)t * M + m) ^ s_r) * P) >> 32;
+}
 
 struct Device {
   int cus = 256;   // compute units of the current device

@@ -44,14 +44,59 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
 constexpr uint32_t kChunk = 16384;  // buckets per LDS histogram (64 KiB)
 constexpr int kPartThreads = 512;
 
+// With shared reservoirs each key is replaced by its reservoir (keys >= M,
+// the empty key included, stay empty).
+struct ShareMap {
+  int shared;
+  uint32_t s_r, M;
+  uint64_t P;
+};
+
+__device__ __forceinline__ uint32_t shared_reservoir(const ShareMap& sm, uint32_t t, uint32_t key) {
+  if (key == kEmpty || key >= sm.M) return kEmpty;
+  return (uint32_t)reservoir_of(true, sm.s_r, sm.P, sm.M, t, key);
+}
+
+// Table-major copy of the keys.  With shared reservoirs each key becomes its
+// reservoir, and a row that reaches one reservoir from several tables keeps
+// only the first such table's entry (the others become empty): a reservoir
+// then sees every row at most once.
 __global__ __launch_bounds__(256) void keys_transpose_kernel(const uint32_t* __restrict__ keys, uint32_t n,
                                                              uint32_t L, uint32_t np,
-                                                             uint32_t* __restrict__ keys_t) {
+                                                             uint32_t* __restrict__ keys_t, ShareMap sm) {
   __shared__ uint32_t tile[64][65];
   const uint32_t row0 = blockIdx.x * 64, t0 = blockIdx.y * 64;
   for (uint32_t i = threadIdx.x; i < 64 * 64; i += 256) {
     const uint32_t r = i >> 6, c = i & 63, row = row0 + r, t = t0 + c;
-    tile[r][c] = (row < n && t < L) ? keys[(uint64_t)row * L + t] : kEmpty;
+    uint32_t key = (row < n && t < L) ? keys[(uint64_t)row * L + t] : kEmpty;
+    if (sm.shared) key = shared_reservoir(sm, t, key);
+    tile[r][c] = key;
+  }
+  if (sm.shared) {
+    __syncthreads();
+    // earlier tables of the same row: inside this tile from LDS, before it
+    // (t0 > 0) recomputed from the keys
+    uint32_t keep[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const uint32_t i = threadIdx.x + 256u * (uint32_t)e;
+      const uint32_t r = i >> 6, c = i & 63, row = row0 + r;
+      uint32_t v = tile[r][c];
+      if (v != kEmpty) {
+        for (uint32_t c2 = 0; c2 < c; ++c2)
+          if (tile[r][c2] == v) v = kEmpty;
+        if (v != kEmpty && row < n)
+          for (uint32_t t2 = 0; t2 < t0; ++t2)
+            if (shared_reservoir(sm, t2, keys[(uint64_t)row * L + t2]) == v) v = kEmpty;
+      }
+      keep[e] = v;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      const uint32_t i = threadIdx.x + 256u * (uint32_t)e;
+      tile[i >> 6][i & 63] = keep[e];
+    }
   }
   __syncthreads();
   for (uint32_t i = threadIdx.x; i < 64 * 64; i += 256) {
@@ -67,6 +112,8 @@ struct PartArgs {
   int32_t* staged;
   uint32_t np, M, ch, n_chunks, n_slices, slice_vecs;
   uint32_t id_base;        // id of row 0 of this batch
+  uint32_t row_mod;        // shared reservoirs: the L key rows are one row of
+                           // L * row_mod entries, and entry e is row e % row_mod
 };
 
 // Workgroups go to the 8 XCDs round-robin by blockIdx.x.  This bijection
@@ -127,10 +174,11 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) 
   for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
     const uint4 x = rowv[v];
     const uint32_t kk[4] = {x.x, x.y, x.z, x.w};
+    const uint32_t row0 = a.row_mod ? (4 * v) % a.row_mod : 4 * v;  // row_mod is a multiple of 64
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t d = kk[j] - lo;
-      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + 4 * v + (uint32_t)j);
+      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + row0 + (uint32_t)j);
     }
   }
 }
@@ -331,7 +379,7 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
       if ((uint32_t)i >= n) break;
       int r = 0;
 #pragma unroll
-      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i];
+      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i] || (pk[j] == pk[i] && j < i);
       if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
     }
   }
@@ -420,28 +468,35 @@ hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
 
 namespace {
 
-// Shape of the LDS-privatised counting sort for n rows.
+// Shape of the LDS-privatised counting sort for n rows.  With shared
+// reservoirs the L key rows form one row of L * np entries over P buckets.
 struct Geo {
-  uint32_t np, ch, n_chunks, n_slices, slice_vecs;
+  uint32_t np;                 // rows padded to 64
+  uint32_t Lp, np_part;        // partition tables and their row length
+  uint64_t Mp;                 // partition buckets per table
+  uint32_t ch, n_chunks, n_slices, slice_vecs;
   uint64_t nb, nparts, tiles;
 };
 
 Geo geometry(const Cfg& c, int64_t n_rows) {
   Geo g;
   g.np = (uint32_t)(((uint64_t)(n_rows > 0 ? n_rows : 1) + 63) / 64 * 64);
-  g.ch = c.M < kChunk ? c.M : kChunk;
-  g.n_chunks = c.M / g.ch;
-  const uint32_t base_blocks = (uint32_t)c.L * g.n_chunks;
+  g.Lp = c.shared ? 1u : (uint32_t)c.L;
+  g.Mp = c.shared ? c.P : (uint64_t)c.M;
+  g.np_part = c.shared ? g.np * (uint32_t)c.L : g.np;
+  g.ch = g.Mp < kChunk ? (uint32_t)g.Mp : kChunk;
+  g.n_chunks = (uint32_t)(g.Mp / g.ch);
+  const uint32_t base_blocks = g.Lp * g.n_chunks;
   // about one partition block per CU: more row slices interleave more runs
   // of `staged` (partial-line writes), fewer leave CUs idle
   const uint32_t cus = (uint32_t)device_info().cus;
   uint32_t s = (cus + base_blocks - 1) / base_blocks;
-  const uint32_t max_s = g.np / 16384 > 1 ? g.np / 16384 : 1;  // slices of >= 16384 rows
+  const uint32_t max_s = g.np_part / 16384 > 1 ? g.np_part / 16384 : 1;  // slices of >= 16384 rows
   if (s > max_s) s = max_s;
   if (s < 1) s = 1;
   g.n_slices = s;
-  g.slice_vecs = (g.np / 4 + s - 1) / s;
-  g.nb = (uint64_t)c.L * c.M;
+  g.slice_vecs = (g.np_part / 4 + s - 1) / s;
+  g.nb = (uint64_t)g.Lp * g.Mp;
   g.nparts = g.nb * s;
   g.tiles = (g.nparts + kTile - 1) / kTile;
   return g;
@@ -488,21 +543,27 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   if (n_rows <= 0) return append ? hipSuccess : launch_fill_u32(counts, g.nb, 0u, s);
   if ((e = launch_fill_u32(w.wl_len, 2, 0u, s)) != hipSuccess) return e;
   // table-major keys
+  ShareMap sm;
+  sm.shared = c.shared ? 1 : 0;
+  sm.s_r = c.s_r;
+  sm.M = c.M;
+  sm.P = c.P;
   hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
-                     (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t);
+                     (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t, sm);
   PartArgs pa;
   pa.keys_t = w.keys_t;
   pa.part = w.part;
   pa.partoff = w.partoff;
   pa.staged = w.staged;
-  pa.np = g.np;
-  pa.M = c.M;
+  pa.np = g.np_part;
+  pa.M = (uint32_t)g.Mp;
   pa.ch = g.ch;
   pa.n_chunks = g.n_chunks;
   pa.n_slices = g.n_slices;
   pa.slice_vecs = g.slice_vecs;
   pa.id_base = id_base;
-  const uint32_t blocks = (uint32_t)c.L * g.n_chunks * g.n_slices;
+  pa.row_mod = c.shared ? g.np : 0u;
+  const uint32_t blocks = g.Lp * g.n_chunks * g.n_slices;
   const size_t lds = sizeof(uint32_t) * g.ch;
   hipLaunchKernelGGL(part_count_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
   // exclusive scan of the (bucket, slice) counts
@@ -525,7 +586,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.wl_len = w.wl_len;
   a.n_buckets = g.nb;
   a.s_p = c.seeds.s_p;
-  a.M = c.M;
+  a.M = c.shared ? 1u : c.M;  // priority salt: the table, or the shared reservoir itself
   a.R = c.R;
   a.append = append ? 1 : 0;
   hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);

@@ -36,11 +36,11 @@ class flash_params(ctypes.Structure):
     _fields_ = [("K", ctypes.c_int32), ("L", ctypes.c_int32),
                 ("bits_per_hash", ctypes.c_int32), ("R", ctypes.c_int32),
                 ("seed", ctypes.c_uint64), ("densify_attempts", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("share_permille", ctypes.c_int32)]
 
     @classmethod
-    def make(cls, K, L, bits_per_hash, R, seed=1, densify_attempts=64):
-        return cls(K, L, bits_per_hash, R, seed, densify_attempts, 0)
+    def make(cls, K, L, bits_per_hash, R, seed=1, densify_attempts=64, share_permille=0):
+        return cls(K, L, bits_per_hash, R, seed, densify_attempts, share_permille)
 
     @property
     def M(self) -> int:

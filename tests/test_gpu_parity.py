@@ -768,3 +768,65 @@ def test_rerank_of_flash_candidates(fl, orc):
         wi, wn = orc.rerank(measure, rp, ci, qrp, qci, cand, 10)
         gi, gn = _gpu_rerank(fl, measure, rp, ci, qrp, qci, cand, 10)
         assert np.array_equal(gi, wi) and np.array_equal(gn, wn), measure
+
+
+# ------------------------------------------------------------------ reservoir sharing
+
+def _shared_pair(fl, orc, K, L, b, R, seed, permille):
+    p = fl.flash_params.make(K, L, b, R, seed=seed, share_permille=permille)
+    op = orc.params(K, L, b, R, seed=seed, share_permille=permille)
+    P = orc.pool_size(op)
+    assert fl.flash_index_elems(p) == (P, P * R)
+    return p, op, P
+
+
+@pytest.mark.parametrize("permille", [1, 100, 600])
+def test_shared_insert_tiny(fl, orc, tiny_index, permille):
+    say("shared insert tiny", permille)
+    _, _, rp, ci, keys, _, _, _, _ = tiny_index
+    p, op, P = _shared_pair(fl, orc, 4, 16, 4, 32, 1, permille)
+    ocounts, oids = orc.build_tables(op, keys)
+    counts, ids = gpu_insert(fl, p, keys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, 32)
+
+
+@pytest.mark.parametrize("R", [4, 64, 300])
+def test_shared_heavy_reservoirs(fl, orc, R):
+    # a pool far smaller than the buckets: many rows arrive twice in one
+    # reservoir, every select path merges arrivals of several tables
+    say("shared heavy R", R)
+    rng = np.random.default_rng(90 + R)
+    K, L, b = 2, 8, 4
+    n = 20000
+    keys = rng.integers(0, 1 << (K * b), size=(n, L), dtype=np.int64).astype(np.uint32)
+    keys[rng.random((n, L)) < 0.02] = EMPTY
+    p, op, P = _shared_pair(fl, orc, K, L, b, R, 7, 5)
+    ocounts, oids = orc.build_tables(op, keys)
+    counts, ids = gpu_insert(fl, p, keys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
+    q = 500
+    wi, wc = orc.query(op, ocounts, oids, keys[:q], 40, self_ids=np.arange(q, dtype=np.int32))
+    gi, gc = gpu_query(fl, p, counts, ids, n, keys[:q], 40, np.arange(q, dtype=np.int32))
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+def test_shared_url_graph_and_append(fl, orc):
+    # a URL-shaped graph with F = 0.2: one-shot graph, then the same index
+    # grown by appends, both against the oracle
+    import torch
+    from paper_1709_01190_amd import datagen
+    say("shared url graph")
+    spec = datagen.scaled(datagen.URL, 200_000)
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
+    p, op, P = _shared_pair(fl, orc, 5, 32, 3, 64, 1, 200)
+    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, 32)
+    okeys = orc.doph(op, rp, ci)
+    ocounts, oids = orc.build_tables(op, okeys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)
+    n = spec.n_rows
+    sample = np.arange(0, n, 41)
+    wi, wc = orc.query(op, ocounts, oids, okeys[sample], 32, self_ids=sample.astype(np.int32))
+    assert np.array_equal(i32(oi)[sample], wi) and np.array_equal(i32(oc)[sample], wc)
+    c2, i2 = _append_batches(fl, p, okeys, [0, 70_000, 70_001, 150_000, n], [2, 0, 3, 1])
+    occupied_equal(u32(c2), i32(i2), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)

@@ -52,10 +52,11 @@ def test_param_checks_run_on_the_host(fl):
             fl.flash_check_params(bad)
         assert e.value.code == code
     p = P(4, 16, 4, 32)
-    bad = P(4, 16, 4, 32)
-    bad.reserved = 1
-    with pytest.raises(fl.FlashError):
-        fl.flash_check_params(bad)
+    for v in (-1, 1001):
+        bad = P(4, 16, 4, 32)
+        bad.share_permille = v
+        with pytest.raises(fl.FlashError):
+            fl.flash_check_params(bad)
 
 
 def test_index_and_workspace_sizes(fl):
@@ -143,3 +144,12 @@ def test_rerank_arguments_are_checked_on_the_host(fl):
     for measure, nc, k in ((2, 10, 5), (0, 0, 1), (0, 1025, 5), (1, 10, 11), (1, 10, 0)):
         r = L.flash_rerank_exact(measure, 10, 100, vp, vp, 5, 50, vp, vp, vp, nc, k, vp, vp, None)
         assert r == fl.FLASH_EINVAL, (measure, nc, k)
+
+
+def test_shared_pool_size_matches_the_oracle(fl, orc):
+    # the library's pool arithmetic against the oracle's (both read Sec. 3.5)
+    for K, L, b, R, permille in ((4, 64, 4, 128, 200), (5, 32, 3, 64, 500), (2, 3, 3, 4, 1),
+                                 (1, 2, 2, 8, 500), (4, 16, 4, 32, 999), (4, 16, 4, 32, 1000), (4, 16, 4, 32, 0)):
+        ce, ie = fl.flash_index_elems(fl.flash_params.make(K, L, b, R, share_permille=permille))
+        P = orc.pool_size(orc.params(K, L, b, R, share_permille=permille))
+        assert ce == P and ie == P * R, (K, L, b, permille)
