@@ -44,7 +44,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving", "uneven", "append", "rerank"])
+    ap.add_argument("--workload", default="webspam", choices=sorted(WORKLOADS) + ["serving", "uneven", "append", "rerank", "share"])
     ap.add_argument("--queries", type=int, default=1_000_000, help="uneven: queries in the batch")
     ap.add_argument("--batches", type=int, default=24, help="append: batches the index is grown in")
     ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
@@ -65,12 +65,12 @@ def main():
     if args.copy_mib:
         copy_calibration(args.copy_mib)
         return
-    if args.workload in ("serving", "uneven", "append", "rerank"):
+    if args.workload in ("serving", "uneven", "append", "rerank", "share"):
         if args.gpus != 1:
             print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}), flush=True)
             sys.exit(2)
         {"serving": serving_bench, "uneven": uneven_bench, "append": append_bench,
-         "rerank": rerank_bench}[args.workload](args)
+         "rerank": rerank_bench, "share": share_bench}[args.workload](args)
         return
 
     if args.gpus != 1:
@@ -598,6 +598,86 @@ def rerank_bench(args):
         "rerank_ms": round(t_r, 3),
         "S_at_10_count_ranked": round(s_at(fi, fn_), 4),
         "S_at_10_reranked": round(s_at(oi, on), 4),
+    }
+    print(json.dumps(out), flush=True)
+
+
+def share_bench(args):
+    """Reservoir sharing (Sec. 3.5): the URL-shaped index at F = 1, 0.5, 0.2,
+    0.1 and 0.05; index bytes, build and query times, and S@10 (mean exact
+    cosine of the top 10) of 20K queries drawn from the index's clusters."""
+    import dataclasses
+
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import datagen, flash
+
+    torch.cuda.set_device(0)
+    spec = datagen.URL
+    if args.rows:
+        spec = datagen.scaled(spec, args.rows)
+    rp, ci = datagen.make_rows(spec, 1, device="cuda")
+    nq, k = 20_000, 10
+    qrp, qci = datagen.make_rows(dataclasses.replace(spec, n_rows=nq), 1, device="cuda", row_seed=2)
+    stream = torch.cuda.current_stream()
+    rowlen = (rp[1:] - rp[:-1]).double()
+    qlen = (qrp[1:] - qrp[:-1]).double()
+
+    def timed(fn, reps):
+        out = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            torch.cuda.synchronize()
+            out.append(e0.elapsed_time(e1))
+        return float(np.median(out[1:])) if len(out) > 1 else out[0]
+
+    rows = []
+    for permille in (1000, 500, 200, 100, 50):
+        p = flash.flash_params.make(5, 32, 3, 64, seed=1, share_permille=permille)
+        counts, ids = flash.alloc_index(p)
+        ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
+        t_build = timed(lambda: flash.flash_build_index(p, rp, ci, counts, ids, ws, stream=stream), 3)
+        del ws
+        oi = torch.empty(nq * k, dtype=torch.int32, device="cuda")
+        oc = torch.empty_like(oi)
+        qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=nq, k=k)
+        t_query = timed(lambda: flash.flash_query_batch(p, counts, ids, spec.n_rows, qrp, qci, k, oi, oc, qws,
+                                                        stream=stream), 3)
+        ri = torch.empty_like(oi)
+        rn = torch.empty_like(oi)
+        flash.flash_rerank_exact(flash.SIM_COSINE, rp, ci, qrp, qci, oi.view(nq, k), k, ri, rn, stream=stream)
+        torch.cuda.synchronize()
+        idv = ri.view(nq, k).long()
+        valid = idv >= 0
+        sz = torch.where(valid, rowlen[idv.clamp(min=0)], torch.ones(1, device="cuda", dtype=torch.float64))
+        cos = torch.where(valid & (rn.view(nq, k) > 0), rn.view(nq, k).double() / torch.sqrt(qlen[:, None] * sz),
+                          torch.zeros(1, device="cuda", dtype=torch.float64))
+        row = {"F": permille / 1000, "reservoirs": int(counts.numel()),
+               "index_bytes": int(counts.numel() * 4 + ids.numel() * 4),
+               "build_ms": round(t_build, 3), "query_ms": round(t_query, 3),
+               "S_at_10": round(float(cos.sum(dim=1).div(k).mean().item()), 4)}
+        log(json.dumps(row))
+        rows.append(row)
+        del counts, ids, qws
+        torch.cuda.empty_cache()
+    base = rows[0]
+    out = {
+        "metric": "reservoir sharing: index bytes and S@10 versus F (url-shape index)",
+        "value": rows[2]["S_at_10"],
+        "unit": "S@10 at F=0.2",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "url-shaped reservoir sharing", "index_rows": spec.n_rows, "queries": nq,
+                   "K": 5, "L": 32, "bits_per_hash": 3, "R": 64, "k": k},
+        "sweep": rows,
+        "S_at_10_F1": base["S_at_10"],
     }
     print(json.dumps(out), flush=True)
 
