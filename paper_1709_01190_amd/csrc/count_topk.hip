@@ -2,26 +2,26 @@
 // query hits, count how many of them hold each id, and return the k ids with
 // the highest counts (ties: smaller id first).
 //
-// One wavefront per query, almost everything in registers:
-//   1. lane t reads key t and counts[t][key]; a wave scan gives each table's
-//      offset in the flattened candidate list (total = sum of occupancies);
-//   2. the wave walks the flattened list 256 candidates at a time; which
-//      table a lane's candidate belongs to is found by a wave-uniform loop
-//      over the tables in the window (readlane, no LDS), so four HBM loads
-//      per lane are in flight at once;
+// One wavefront per query (count_topk_kernel):
+//   1. lane t reads key t and the bucket's count; one packed DPP scan gives
+//      every table its first candidate and its first task (a task is 4
+//      consecutive occupied slots, one 16-byte load);
+//   2. the wave walks the tasks 256 at a time: each table's first task is
+//      marked in LDS and a DPP prefix-max assigns every lane its table, so
+//      four 16-byte loads per lane are in flight at once;
 //   3. each id goes into an LDS open-addressing table whose slot packs
 //      (id << cbits | count): one CAS claims an empty slot, a matching id
-//      adds 1.  Newly claimed slots are appended to a list with ballot/mbcnt
-//      offsets (no atomics), so every later pass costs O(distinct ids);
-//   4. a histogram of counts, kept one count value per lane and filled by a
-//      match loop (one ballot per distinct value), gives the threshold count
-//      c*; if too many ids tie at c*, an id threshold is found by counting
-//      with ballots (guessed from the uniform spread of ids, then bisected)
-//      so that between k and k + slack entries survive;
-//   5. survivors are ranked by (count desc, id asc) with broadcast LDS reads
-//      (no barriers) and written to their rank; slots are cleared on the way.
-// Queries with more candidates than a launch's table takes are appended to a
-// list that the next launch (a larger table) processes.
+//      adds 1 (count_ids16: all first probes at once, then up to two
+//      colliding ids per lane retried with double hashing);
+//   4. one sweep compacts the distinct entries to the front of the table and
+//      histograms their counts, which gives the threshold count c*; if too
+//      many ids tie at c*, an id threshold is guessed from the uniform spread
+//      of ids and bisected until between k and k + slack entries survive;
+//   5. the survivors are sorted in registers and written; the table is
+//      cleared on the way.
+// Queries with more candidates than a launch's table takes are handed on to
+// the next launch (a larger table).  A last stage with a table of 32-64 KB
+// runs one workgroup of several waves per query (count_topk_block_kernel).
 #include "launch.hpp"
 
 namespace flashk {
