@@ -128,6 +128,28 @@ def main():
         step(evs[s])
     torch.cuda.synchronize()
     wall = time.perf_counter() - w0
+    # the same step captured once in a HIP graph and replayed (no launch overhead)
+    gs = torch.cuda.Stream()
+
+    def gstep():
+        flash.flash_hash(p, rp, ci, keys, stream=gs)
+        flash.flash_insert_keys(p, keys, counts, ids, ins_ws, stream=gs)
+        flash.flash_query_keys(p, counts, ids, n, keys, k, oi, oc, q_ws, self_ids=self_ids, stream=gs)
+
+    gs.wait_stream(stream)
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=gs):
+        gstep()
+    graph.replay()
+    torch.cuda.synchronize()
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(args.steps):
+        graph.replay()
+    g1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = g0.elapsed_time(g1) / args.steps
+    log(f"graph replay: {graph_ms:.3f} ms/step")
     phase_ms = np.array([[e[i].elapsed_time(e[i + 1]) for i in range(3)] for e in evs])
     step_ms = float(np.mean([e[0].elapsed_time(e[3]) for e in evs]))
     ph = phase_ms.mean(axis=0)
@@ -191,6 +213,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "phases": phases,
+        "graph_ms_per_step": round(graph_ms, 4),
     }
     print(json.dumps(out), flush=True)
 
