@@ -835,12 +835,8 @@ template <int CAP, int LCH, bool ALIGNED>
 hipError_t launch_kernel(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = smem_bytes(CAP, a.L, a.sb);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH, ALIGNED>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH, ALIGNED>), lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((count_topk_kernel<CAP, LCH, ALIGNED>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError();
 }
@@ -876,12 +872,8 @@ template <int CAP, int LCH, bool ALIGNED, int NW>
 hipError_t launch_block_kernel(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = block_smem_bytes(CAP, a.L, a.sb, NW);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    const hipError_t e = hipFuncSetAttribute(
-        reinterpret_cast<const void*>(&count_topk_block_kernel<CAP, LCH, ALIGNED, NW>),
-        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-  }
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_block_kernel<CAP, LCH, ALIGNED, NW>), lds);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((count_topk_block_kernel<CAP, LCH, ALIGNED, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
   return hipGetLastError();
 }

@@ -108,6 +108,34 @@ const Device& device_info() {
   return infos[dev];
 }
 
+hipError_t allow_lds(const void* kernel, size_t bytes) {
+  if (bytes <= 64 * 1024) return hipSuccess;
+  static std::mutex mu;
+  static const void* kern[64];
+  static size_t size[64];
+  static int n = 0;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  std::lock_guard<std::mutex> lock(mu);
+  // keyed by (kernel, device): the attribute is per device
+  const void* key = (const char*)kernel + dev;
+  for (int i = 0; i < n; ++i)
+    if (kern[i] == key && size[i] >= bytes) return hipSuccess;
+  const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+  if (e != hipSuccess) return e;
+  for (int i = 0; i < n; ++i)
+    if (kern[i] == key) {
+      size[i] = bytes;
+      return hipSuccess;
+    }
+  if (n < 64) {
+    kern[n] = key;
+    size[n] = bytes;
+    ++n;
+  }
+  return hipSuccess;
+}
+
 std::mutex g_tuning_mu;
 Tuning g_tuning;
 

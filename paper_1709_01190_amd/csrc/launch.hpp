@@ -88,6 +88,12 @@ hipError_t launch_rerank(int measure, int64_t n_indexed, int64_t nnz, const int6
 // ---- misc
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 
+// Lets `kernel` launch with `bytes` of dynamic LDS (above the 64 KiB
+// default).  The attribute is set once per kernel and size, not on every
+// launch, so launches inside a stream capture issue no such call after the
+// first eager one.
+hipError_t allow_lds(const void* kernel, size_t bytes);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace flashk
