@@ -163,7 +163,8 @@ FLASH_API int flash_build_index_append(const flash_params *p, int64_t n_rows, in
  * self_ids[q] (if self_ids is not NULL and the entry is >= 0) are left out.
  * out_ids / out_counts (int32[n_queries][k]) get the first k ids by (cnt
  * descending, id ascending), padded with id -1, count 0.  Requires
- * 1 <= k <= 1024 and fewer than 2^32 / 2^ceil(log2(L+2)) indexed rows. */
+ * 1 <= k <= 1024, n_queries < 2^31 and fewer than 2^32 / 2^ceil(log2(L+2))
+ * indexed rows (FLASH_ENOTIMPL otherwise). */
 FLASH_API int flash_query_keys(const flash_params *p, const uint32_t *counts, const int32_t *ids,
                                int64_t n_indexed, int64_t n_queries, const uint32_t *qkeys,
                                const int32_t *self_ids, int32_t k, int32_t *out_ids,
@@ -242,7 +243,7 @@ typedef struct flash_tuning {
                                     1024..16384, rounded down to a power of two.  Default 2048 */
     int32_t query_cap2;          /* the same for the second stage; default 4096 */
     int32_t query_blocks_per_cu; /* one-wave workgroups per CU in the first stage, 1..1024;
-                                    default 128 */
+                                    default 256 */
     int32_t query_big_waves;     /* waves per workgroup that share one query in the last stage
                                     when its table has >= 8192 entries: 1, 4, 8 or 16; default 8 */
     int32_t hash_tile_rows;      /* flash_query_batch*: 0 = static row stride; else each wave

@@ -982,7 +982,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   const int nw = (last >= 8192 && tu.query_big_waves > 1) ? tu.query_big_waves : 1;
 
   const int cus = device_info().cus;
-  const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 128;
+  const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 256;
   hipError_t e;
   if (n_stage > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
   for (int s = 0; s < n_stage; ++s) {

@@ -81,6 +81,7 @@ int check_csr(int64_t n_rows, int64_t nnz, const int64_t* row_ptr, const int32_t
 
 int check_query(const Cfg& c, int64_t n_indexed, int64_t n_queries, int32_t k) {
   if (n_queries < 0 || n_indexed < 0) return fail(FLASH_EINVAL, "sizes must be >= 0");
+  if (n_queries >= ((int64_t)1 << 31)) return fail(FLASH_ENOTIMPL, "n_queries must be < 2^31");
   if (k < 1 || k > 1024) return fail(FLASH_EINVAL, "k must be in [1, 1024]");
   const int cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
   if (n_indexed > ((int64_t)1 << (32 - cbits)))
@@ -544,7 +545,7 @@ FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* 
   // candidate values, one field at a time
   const int waves[] = {1, 4, 8, 16};
   const int stages[][2] = {{2048, 4096}, {2048, 0}, {1024, 4096}, {4096, 0}, {1024, 0}, {0, 0}};
-  const int per_cu[] = {32, 64, 128, 256};
+  const int per_cu[] = {64, 128, 256, 512};
   const int tiles[] = {0, 4, 16, 64};
   for (int field = 0; field < 4 && !rc; ++field) {
     const int n = field == 1 ? 6 : 4;

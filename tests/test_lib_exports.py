@@ -87,6 +87,12 @@ def test_device_calls_reject_bad_arguments_before_launch(fl):
                             ctypes.c_void_p(16), 1 << 20, None)
     assert rc == fl.FLASH_EINVAL
     assert b"k must be" in L.flash_last_error()
+    # query ids travel between table-size stages as 32-bit words
+    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), 10, 1 << 31,
+                            ctypes.c_void_p(16), None, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                            ctypes.c_void_p(16), 1 << 20, None)
+    assert rc == fl.FLASH_ENOTIMPL
+    assert b"n_queries" in L.flash_last_error()
 
 
 def test_binding_refuses_cpu_tensors(fl):
@@ -102,7 +108,7 @@ def test_binding_refuses_cpu_tensors(fl):
 def test_tuning_is_checked_and_restorable(fl):
     fl.flash_set_tuning(None)
     d = fl.flash_get_tuning().as_dict()
-    assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 128,
+    assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 256,
                  "query_big_waves": 8, "hash_tile_rows": 0}
     fl.flash_set_tuning(query_big_waves=16, hash_tile_rows=32, query_cap2=0)
     d2 = fl.flash_get_tuning().as_dict()
