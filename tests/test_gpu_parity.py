@@ -335,6 +335,72 @@ def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, tuned):
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
 
 
+def test_empty_batches_and_empty_rows(fl, orc):
+    # zero-row and zero-query calls enqueue nothing (a build of zero rows
+    # still clears the counts); rows and queries without columns take part
+    # in no bucket, so their lists are all padding
+    import torch
+    say("empty batches and empty rows")
+    p = fl.flash_params.make(4, 16, 4, 32, seed=1)
+    op = orc.params(4, 16, 4, 32, seed=1)
+    rp0 = torch.zeros(1, dtype=torch.int64, device="cuda")
+    ci0 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    counts, ids = fl.alloc_index(p)
+    counts.fill_(5)
+    ids.fill_(9)
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=0)
+    keys0 = torch.zeros(0, dtype=torch.int32, device="cuda")
+    fl.flash_hash(p, rp0, ci0, keys0)
+    fl.flash_insert_keys_append(p, keys0, 0, counts, ids, ws)
+    fl.flash_build_index_append(p, rp0, ci0, 0, counts, ids, ws)
+    torch.cuda.synchronize()
+    assert (i32(counts) == 5).all() and (i32(ids) == 9).all()
+    fl.flash_build_index(p, rp0, ci0, counts, ids, ws)
+    torch.cuda.synchronize()
+    assert (i32(counts) == 0).all()
+    # a real index, then empty query batches and a batch of empty queries
+    from paper_1709_01190_amd import datagen
+    spec = datagen.scaled(datagen.TINY, 2000)
+    rp, ci = datagen.make_rows(spec, 1)
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
+    fl.flash_build_index(p, rp.cuda(), ci.cuda(), counts, ids, ws)
+    torch.cuda.synchronize()
+    snap = (i32(counts).copy(), i32(ids).copy())
+    k = 8
+    sentinel = torch.full((4 * k,), 77, dtype=torch.int32, device="cuda")
+    oi, oc = sentinel.clone(), sentinel.clone()
+    qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=0, k=k)
+    fl.flash_query_keys(p, counts, ids, spec.n_rows, keys0, k, oi, oc, qws)
+    fl.flash_query_batch(p, counts, ids, spec.n_rows, rp0, ci0, k, oi, oc, qws)
+    fl.flash_query_batch_mixed(p, counts, ids, spec.n_rows, rp0, ci0,
+                               torch.zeros(0, dtype=torch.int32, device="cuda"), k, oi, oc, qws)
+    gws = fl.alloc_workspace(fl.OP_KNN_GRAPH, p, n_rows=0, k=k)
+    c2, i2 = fl.alloc_index(p)
+    fl.flash_knn_graph(p, rp0, ci0, k, c2, i2, oi, oc, gws)
+    fl.flash_rerank_exact(fl.SIM_COSINE, rp.cuda(), ci.cuda(), rp0, ci0,
+                          torch.zeros((0, k), dtype=torch.int32, device="cuda"), k, oi, oc)
+    torch.cuda.synchronize()
+    assert (i32(oi) == 77).all() and (i32(oc) == 77).all()
+    assert (i32(c2) == 0).all()
+    q = 4
+    qrp = torch.zeros(q + 1, dtype=torch.int64, device="cuda")   # four rows without columns
+    qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=k)
+    fl.flash_query_batch(p, counts, ids, spec.n_rows, qrp, ci0, k, oi, oc, qws)
+    torch.cuda.synchronize()
+    wi, wc = orc.query(op, *orc.build_tables(op, orc.doph(op, rp.numpy(), ci.numpy())),
+                       orc.doph(op, qrp.cpu().numpy(), np.zeros(0, np.int32)), k)
+    assert (wi == -1).all() and (wc == 0).all()
+    assert np.array_equal(i32(oi).reshape(q, k), wi.reshape(q, k))
+    assert np.array_equal(i32(oc).reshape(q, k), wc.reshape(q, k))
+    assert np.array_equal(i32(counts), snap[0]) and np.array_equal(i32(ids), snap[1])
+    # an index of rows without columns holds nothing
+    rpe = torch.zeros(101, dtype=torch.int64, device="cuda")
+    ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=100)
+    fl.flash_build_index(p, rpe, ci0, counts, ids, ws)
+    torch.cuda.synchronize()
+    assert (i32(counts) == 0).all()
+
+
 # ------------------------------------------------------------------ whole path
 
 def _gpu_graph(fl, p, rp, ci, k):
