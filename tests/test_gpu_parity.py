@@ -306,6 +306,24 @@ def test_query_overflow_table(fl, orc, tuned):
         assert np.array_equal(oi, wi) and np.array_equal(oc, wc), shape
 
 
+@pytest.mark.parametrize("k", [113, 120, 128])
+def test_query_top_k_among_thousands_of_ties(fl, orc, k):
+    # every query has ~2,000 candidates, most seen once or twice, so the tie
+    # cut leaves k .. k + 16 survivors (k <= 128: 129-144 of them at most)
+    say("query top-k among ties", k)
+    rng = np.random.default_rng(21)
+    K, L, b, R = 1, 32, 3, 64
+    n = 4000
+    keys = rng.integers(0, 1 << (K * b), size=(n, L)).astype(np.uint32)
+    op = orc.params(K, L, b, R, seed=8)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(K, L, b, R, seed=8)
+    counts, ids = gpu_insert(fl, p, keys)
+    wi, wc = orc.query(op, ocounts, oids, keys[:600], k, self_ids=np.arange(600, dtype=np.int32))
+    oi, oc = gpu_query(fl, p, counts, ids, n, keys[:600], k, np.arange(600, dtype=np.int32))
+    assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
+
+
 def test_query_many_tables(fl, orc):
     say("query L=200")
     rng = np.random.default_rng(10)
