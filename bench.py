@@ -51,7 +51,8 @@ def main():
                     help="serving: offered queries per second, comma separated")
     ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
     ap.add_argument("--recall-queries", type=int, default=1000,
-                    help="serving: sampled queries scored against brute-force Jaccard")
+                    help="sampled queries (graph workloads: rows) scored against brute-force "
+                         "exact Jaccard; 0 skips it")
     ap.add_argument("--rows", type=int, default=0, help="override the row count (parity/debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-queries", type=int, default=20000,
@@ -194,6 +195,15 @@ def main():
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
 
+    recall = None
+    if args.recall_queries > 0:
+        sel = np.sort(np.random.default_rng(3).choice(n, size=min(args.recall_queries, n), replace=False))
+        sel_d = torch.from_numpy(sel).cuda()
+        t1 = time.time()
+        recall = recall_exact_jaccard(rp, ci, spec.n_cols, rp, ci, oi.view(n, k)[sel_d], self_ids=sel,
+                                      q_rows=sel)
+        log(f"R@{k} over {len(sel)} sampled rows: {recall} ({time.time() - t1:.1f}s)")
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(rp, ci, K, L, b, R, k, n, args.cpu_queries)
@@ -217,6 +227,7 @@ def main():
         "cpu_baseline": cpu,
         "phases": phases,
         "graph_ms_per_step": round(graph_ms, 4),
+        "recall": recall,
     }
     print(json.dumps(out), flush=True)
 
@@ -278,21 +289,18 @@ def serving_bench(args):
         table.append(row)
     recall = None
     if args.recall_queries > 0:
-        import oracle
         rng = np.random.default_rng(3)
         sel = np.sort(rng.choice(pool_n, size=args.recall_queries, replace=False))
         k = 50
         srp = np.concatenate([[0], np.cumsum(qrp[sel + 1] - qrp[sel])]).astype(np.int64)
         sci = np.concatenate([qci[qrp[i]:qrp[i + 1]] for i in sel]).astype(np.int32)
+        srp_d, sci_d = torch.from_numpy(srp).cuda(), torch.from_numpy(sci).cuda()
         oi = torch.empty(len(sel) * k, dtype=torch.int32, device="cuda")
         oc = torch.empty_like(oi)
         qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=len(sel), k=k)
-        flash.flash_query_batch(p, counts, ids, spec.n_rows, torch.from_numpy(srp).cuda(),
-                                torch.from_numpy(sci).cuda(), k, oi, oc, qws)
+        flash.flash_query_batch(p, counts, ids, spec.n_rows, srp_d, sci_d, k, oi, oc, qws)
         torch.cuda.synchronize()
-        found = oi.cpu().numpy().reshape(len(sel), k)
-        recall = _recall_against_index(oracle, rp.cpu().numpy(), ci.cpu().numpy(), spec.n_cols, srp, sci,
-                                       found)
+        recall = recall_exact_jaccard(rp, ci, spec.n_cols, srp_d, sci_d, oi.view(len(sel), k))
         log(f"R@{k} over {len(sel)} sampled queries: {recall}")
     top = max(table, key=lambda r: r["offered_qps"]) if table else None
     out = {
@@ -708,38 +716,48 @@ def share_bench(args):
     print(json.dumps(out), flush=True)
 
 
-def _recall_against_index(oracle, rp, ci, n_cols, qrp, qci, found):
-    """R@k of external queries against brute-force exact Jaccard over the
-    indexed rows: append the queries to the row set and score them."""
-    import numpy as np
-    n = rp.shape[0] - 1
-    rp2 = np.concatenate([rp, qrp[1:] + rp[-1]])
-    ci2 = np.concatenate([ci, qci])
-    qids = np.arange(n, n + qrp.shape[0] - 1, dtype=np.int64)
-    # the best indexed row: the first indexed id in each query's exact top-8
-    # (other queries, appended above, are skipped)
-    top, ti, tu = oracle.jaccard_knn(rp2, ci2, n_cols, qids, 8)
-    pick = np.argmax((top >= 0) & (top < n), axis=1)
-    rows_ = np.arange(top.shape[0])
-    best = np.where(((top >= 0) & (top < n)).any(axis=1), top[rows_, pick], -1)[:, None]
-    bi = ti[rows_, pick][:, None]
-    bu = tu[rows_, pick][:, None]
-    # queries must not match each other: rescore only against indexed rows
-    xs = np.repeat(qids, found.shape[1])
-    ys = found.reshape(-1).astype(np.int64)
-    ok = ys >= 0
-    inter = np.zeros(xs.shape[0], np.int64)
-    uni = np.ones(xs.shape[0], np.int64)
-    if ok.any():
-        a, b = oracle.jaccard_pairs(rp2, ci2, xs[ok], ys[ok])
-        inter[ok], uni[ok] = a, b
-    inter = inter.reshape(found.shape)
-    uni = uni.reshape(found.shape)
-    scored = (best[:, 0] >= 0) & (best[:, 0] < n)
-    hit = ((inter * bu[:, :1] == bi[:, :1] * uni) & (inter > 0)).any(axis=1) & scored
-    m = int(scored.sum())
-    return {"R_at_k": round(float(hit.sum()) / m, 4) if m else None, "k": int(found.shape[1]),
-            "scored_queries": m, "gold": "exact Jaccard"}
+def recall_exact_jaccard(rp, ci, n_cols, q_rp, q_ci, found, self_ids=None, q_rows=None):
+    """R@k of the lists `found` (device int32 [Q, k], -1 padded) against brute-force
+    exact Jaccard over every indexed row (device CSR rp, ci), with plain torch
+    ops on the GPU: a measurement of the method's output, not part of the library.
+    For each query its columns are marked in a per-column table, the table is
+    gathered at every nonzero and prefix-summed in float64 (exact for 0/1 terms),
+    and the sum over a row's range is its intersection with the query.  A query
+    hits when a listed id ties the best exact Jaccard of any other row (self_ids[q]
+    is left out); queries that share no column with another row are not scored.
+    Query q is row q of (q_rp, q_ci), or row q_rows[q] if q_rows is given."""
+    import torch
+    n = rp.numel() - 1
+    lens = rp[1:] - rp[:-1]
+    mark = torch.zeros(n_cols, dtype=torch.float64, device=ci.device)
+    cs = torch.zeros(ci.numel() + 1, dtype=torch.float64, device=ci.device)
+    qrp = q_rp.cpu().tolist()
+    hits = scored = 0
+    for q in range(found.shape[0]):
+        r = q if q_rows is None else int(q_rows[q])
+        cols = q_ci[qrp[r]:qrp[r + 1]].long()
+        mark[cols] = 1.0
+        torch.index_select(mark, 0, ci, out=cs[1:])
+        mark[cols] = 0.0
+        cs[1:].cumsum_(0)
+        inter = (cs[rp[1:]] - cs[rp[:-1]]).round().long()
+        union = lens + cols.numel() - inter
+        score = inter.double() / union.clamp(min=1).double()
+        if self_ids is not None:
+            score[int(self_ids[q])] = -1.0
+        best = int(torch.argmax(score).item())
+        bi, bu = int(inter[best].item()), int(union[best].item())
+        if bi == 0:
+            continue
+        scored += 1
+        f = found[q].long()
+        f = f[(f >= 0) & (f < n)]
+        if f.numel():
+            fi, fu = inter[f], union[f]
+            hits += int(((fi * bu == fu * bi) & (fi > 0)).any().item())
+    return {"R_at_k": round(hits / scored, 4) if scored else None, "k": int(found.shape[1]),
+            "sampled_queries": int(found.shape[0]), "scored_queries": scored,
+            "gold": "exact Jaccard, brute force over every indexed row"}
 
 
 def copy_calibration(mib, reps=1):
