@@ -60,8 +60,8 @@ def main():
     ap.add_argument("--traffic-table", default=os.path.join(ROOT, "profiles", "hbm_traffic.txt"),
                     help="calibrated per-launch HBM bytes from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--copy-reps", type=int, default=1,
-                    help="with --copy-mib: also time this many warm copies "
-                         "(the practical HBM ceiling)")
+                    help="with --copy-mib: also time this many warm copies and read-only "
+                         "sums (the practical HBM ceilings)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="instead of the benchmark, copy this many MiB device to device (a plain "
                          "copy kernel of known size that calibrates the HBM byte counters)")
@@ -762,8 +762,9 @@ def recall_exact_jaccard(rp, ci, n_cols, q_rp, q_ci, found, self_ids=None, q_row
 
 def copy_calibration(mib, reps=1):
     """One device-to-device copy of `mib` MiB (the counter calibration); with
-    reps > 1 also the practical HBM ceiling: the best of `reps` warm copies
-    (bytes read + written per second)."""
+    reps > 1 also the practical HBM ceilings: the best of `reps` warm copies
+    (bytes read + written per second) and of `reps` warm float64 sums over the
+    same bytes (a read-only stream)."""
     import torch
     n = mib * (1 << 20) // 4
     src = torch.arange(n, dtype=torch.int32, device="cuda")
@@ -783,6 +784,8 @@ def copy_calibration(mib, reps=1):
     if reps > 1:
         cp = min(timed(lambda: dst.copy_(src)) for _ in range(reps))
         out["warm_copy_GBps"] = round(8 * n / (cp * 1e6), 1)
+        rd = min(timed(lambda: src.view(torch.float64).sum()) for _ in range(reps))
+        out["warm_read_GBps"] = round(4 * n / (rd * 1e6), 1)
     print(json.dumps(out), flush=True)
 
 
