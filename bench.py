@@ -49,7 +49,8 @@ def main():
     ap.add_argument("--batches", type=int, default=24, help="append: batches the index is grown in")
     ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
                     help="serving: offered queries per second, comma separated")
-    ap.add_argument("--requests", type=int, default=600, help="serving: requests per rate")
+    ap.add_argument("--requests", type=int, default=5000, help="serving: requests per rate")
+    ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight at once (streams)")
     ap.add_argument("--recall-queries", type=int, default=1000,
                     help="sampled queries (graph workloads: rows) scored against brute-force "
                          "exact Jaccard; 0 skips it")
@@ -268,7 +269,7 @@ def serving_bench(args):
 
     ex = serving.GpuExecutor(p, counts, ids, spec.n_rows)
     budget = 4 << 30
-    cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=8)
+    cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=args.slots)
     batch = serving.BatchAllServer(ex, budget_bytes=budget)
     warm = serving.make_requests(rows, 50, qps=5e5, seed=99)
     cont.run(warm)
@@ -314,7 +315,7 @@ def serving_bench(args):
         "data": "synthetic",
         "config": {"workload": "url-shaped serving", "index_rows": spec.n_rows, "K": 5, "L": 32,
                    "bits_per_hash": 3, "R": 64, "k": [10, 50, 200], "batch": [1, 4096],
-                   "requests_per_rate": args.requests, "hbm_budget_bytes": budget, "slots": 8},
+                   "requests_per_rate": args.requests, "hbm_budget_bytes": budget, "slots": args.slots},
         "rates": table,
         "recall": recall,
     }

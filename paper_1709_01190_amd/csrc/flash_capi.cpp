@@ -111,26 +111,27 @@ const Device& device_info() {
 
 hipError_t allow_lds(const void* kernel, size_t bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
+  // the attribute is per (kernel, device); past 64 pairs it is simply set again
   static std::mutex mu;
   static const void* kern[64];
+  static int devs[64];
   static size_t size[64];
   static int n = 0;
   int dev = 0;
   (void)hipGetDevice(&dev);
   std::lock_guard<std::mutex> lock(mu);
-  // keyed by (kernel, device): the attribute is per device
-  const void* key = (const char*)kernel + dev;
   for (int i = 0; i < n; ++i)
-    if (kern[i] == key && size[i] >= bytes) return hipSuccess;
+    if (kern[i] == kernel && devs[i] == dev && size[i] >= bytes) return hipSuccess;
   const hipError_t e = hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
   if (e != hipSuccess) return e;
   for (int i = 0; i < n; ++i)
-    if (kern[i] == key) {
+    if (kern[i] == kernel && devs[i] == dev) {
       size[i] = bytes;
       return hipSuccess;
     }
   if (n < 64) {
-    kern[n] = key;
+    kern[n] = kernel;
+    devs[n] = dev;
     size[n] = bytes;
     ++n;
   }
