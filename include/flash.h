@@ -249,7 +249,11 @@ typedef struct flash_tuning {
     int32_t hash_tile_rows;      /* flash_query_batch*: 0 = static row stride; else each wave
                                     takes tiles of this many rows from a work counter,
                                     1..65536; default 0 */
-    int32_t reserved[3];
+    int32_t query_skip_full;     /* 1 = when the index averages at least R arrivals per bucket
+                                    (n_indexed >= R * M, or R * P / L when shared), leave out
+                                    the stages whose table holds fewer than L * R candidates;
+                                    0 = always run the stages above; default 1 */
+    int32_t reserved[2];
 } flash_tuning;
 
 /* Current tuning (host struct). */

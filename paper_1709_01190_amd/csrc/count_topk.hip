@@ -968,6 +968,13 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   uint32_t last = 1024;
   while (last < 2 * full) last <<= 1;                   // table that takes any query at load 1/2
   const Tuning tu = tuning();
+  // When the index holds at least R arrivals per bucket on average, its
+  // buckets are nearly all full and nearly every query brings about L * R
+  // candidates: a stage whose table cannot take that many would only hand
+  // its queries on, so it is left out.
+  const double per_bucket = c.shared ? (double)n_indexed * (double)c.L / (double)c.P
+                                     : (double)n_indexed / (double)c.M;
+  const bool skip_small = tu.query_skip_full != 0 && per_bucket >= (double)c.R;
   int caps[3];
   int n_stage = 0;
   // first and second table sizes (0: no such stage), rounded to a supported size
@@ -975,6 +982,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     if (v <= 0) continue;
     const int cap = supported_cap(v);
     if ((uint32_t)cap >= last) break;
+    if (skip_small && (uint32_t)cap * 3 / 4 < full) continue;
     if (n_stage == 0 || cap > caps[n_stage - 1]) caps[n_stage++] = cap;
   }
   caps[n_stage++] = (int)last;

@@ -157,7 +157,7 @@ int tuning_from_c(const flash_tuning* t, Tuning* out) {
     *out = Tuning();
     return FLASH_OK;
   }
-  if (t->reserved[0] || t->reserved[1] || t->reserved[2])
+  if (t->reserved[0] || t->reserved[1])
     return fail(FLASH_EINVAL, "tuning.reserved must be 0");
   for (int v : {t->query_cap1, t->query_cap2})
     if (v != 0 && (v < 1024 || v > 16384)) return fail(FLASH_EINVAL, "query caps must be 0 or in [1024, 16384]");
@@ -167,11 +167,13 @@ int tuning_from_c(const flash_tuning* t, Tuning* out) {
   if (w != 1 && w != 4 && w != 8 && w != 16) return fail(FLASH_EINVAL, "query_big_waves must be 1, 4, 8 or 16");
   if (t->hash_tile_rows < 0 || t->hash_tile_rows > 65536)
     return fail(FLASH_EINVAL, "hash_tile_rows must be in [0, 65536]");
+  if (t->query_skip_full != 0 && t->query_skip_full != 1) return fail(FLASH_EINVAL, "query_skip_full must be 0 or 1");
   out->query_cap1 = t->query_cap1;
   out->query_cap2 = t->query_cap2;
   out->query_blocks_per_cu = t->query_blocks_per_cu;
   out->query_big_waves = t->query_big_waves;
   out->hash_tile_rows = t->hash_tile_rows;
+  out->query_skip_full = t->query_skip_full;
   return FLASH_OK;
 }
 
@@ -182,6 +184,7 @@ flash_tuning tuning_to_c(const Tuning& t) {
   o.query_blocks_per_cu = t.query_blocks_per_cu;
   o.query_big_waves = t.query_big_waves;
   o.hash_tile_rows = t.hash_tile_rows;
+  o.query_skip_full = t.query_skip_full;
   return o;
 }
 

@@ -38,6 +38,7 @@ struct Tuning {
   int query_blocks_per_cu = 256;  // first-stage blocks per CU
   int query_big_waves = 8;        // waves per workgroup in a last stage of >= 8192 entries (1: one wave)
   int hash_tile_rows = 0;         // 0: static row stride; else rows per tile taken from a work counter
+  int query_skip_full = 1;        // leave out stages too small for L * R candidates when buckets are full
 };
 Tuning tuning();
 

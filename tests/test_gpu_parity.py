@@ -278,8 +278,10 @@ def tuned(fl):
 
 # launch shapes of the query stages: first/second table sizes (0: no such
 # stage) and the waves per workgroup of a large last stage
-STAGE_SHAPES = [dict(query_cap1=c1, query_cap2=c2, query_big_waves=w)
-                for (c1, c2) in ((1024, 4096), (2048, 0), (0, 0), (16384, 0)) for w in (1, 4, 8, 16)]
+# (query_skip_full=0 keeps the small stages even where the buckets are full;
+# the defaults, with the skip, come first)
+STAGE_SHAPES = [dict()] + [dict(query_cap1=c1, query_cap2=c2, query_big_waves=w, query_skip_full=0)
+                           for (c1, c2) in ((1024, 4096), (2048, 0), (0, 0), (16384, 0)) for w in (1, 4, 8, 16)]
 
 
 def test_query_overflow_table(fl, orc, tuned):
