@@ -210,7 +210,7 @@ def main():
         cpu = cpu_baseline(rp, ci, K, L, b, R, k, n, args.cpu_queries)
 
     out = {
-        "metric": "k-NN graph build time + queries/s (webspam-shape)",
+        "metric": f"k-NN graph build time + queries/s ({args.workload}-shape)",
         "value": round(n / (step_ms / 1e3), 1),
         "unit": "queries/s",
         "n_gpus": 1,
