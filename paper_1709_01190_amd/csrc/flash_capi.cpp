@@ -551,17 +551,19 @@ FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* 
   const int stages[][2] = {{2048, 4096}, {2048, 0}, {1024, 4096}, {4096, 0}, {1024, 0}, {0, 0}};
   const int per_cu[] = {64, 128, 256, 512};
   const int tiles[] = {0, 4, 16, 64};
-  for (int field = 0; field < 4 && !rc; ++field) {
-    const int n = field == 1 ? 6 : 4;
+  // the full-bucket stage skip first: it decides whether the stage layouts differ
+  for (int field = 0; field < 5 && !rc; ++field) {
+    const int n = field == 0 ? 2 : (field == 2 ? 6 : 4);
     for (int i = 0; i < n && !rc; ++i) {
       Tuning t = cur;
-      if (field == 0) t.query_big_waves = waves[i];
-      if (field == 1) {
+      if (field == 0) t.query_skip_full = 1 - i;
+      if (field == 1) t.query_big_waves = waves[i];
+      if (field == 2) {
         t.query_cap1 = stages[i][0];
         t.query_cap2 = stages[i][1];
       }
-      if (field == 2) t.query_blocks_per_cu = per_cu[i];
-      if (field == 3) t.hash_tile_rows = tiles[i];
+      if (field == 3) t.query_blocks_per_cu = per_cu[i];
+      if (field == 4) t.hash_tile_rows = tiles[i];
       float ms = 0.f;
       rc = measure(t, &ms);
       if (!rc && ms < cur_ms) {
