@@ -590,7 +590,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.R = c.R;
   a.append = append ? 1 : 0;
   hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
-  hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 16), dim3(64), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 
