@@ -12,7 +12,7 @@ What each function follows (arXiv 1709.01190):
   rerank          Sec. 4.3 gold standard: exact cosine (Eq. 3) or Jaccard
                   ordering of candidate lists
   pool_size,      Sec. 3.5 reservoir sharing (a seeded random map of buckets
-  reservoir       to a pool of about F * L * M reservoirs)
+  reservoir       to a pool of ceil(F * L * M) reservoirs)
 """
 from __future__ import annotations
 
@@ -51,9 +51,14 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-            build(force=True)
-        L = ctypes.CDLL(_LIB)
+        # FLASH_ORACLE_LIB names another build of this source (the mutation
+        # tests load deliberately broken copies through it)
+        path = os.environ.get("FLASH_ORACLE_LIB")
+        if not path:
+            path = _LIB
+            if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+                build(force=True)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         L.orc_mix64.restype = ctypes.c_uint64
         L.orc_mix64.argtypes = [ctypes.c_uint64]

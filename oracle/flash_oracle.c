@@ -29,8 +29,10 @@
  *                                      intersection on tiny inputs.
  *   orc_pool_size, orc_reservoir       Sec. 3.5 reservoir sharing; pinned by
  *                                      F = 1 giving the plain index, the
- *                                      rounding of F * L * M, a uniform map,
- *                                      brute-force shared tables and queries.
+ *                                      pool of ceil(F * L * M) reservoirs
+ *                                      (exact rational arithmetic), a uniform
+ *                                      map, brute-force shared tables and
+ *                                      queries.
  *   orc_rerank                         Sec. 4.3 exact cosine (Eq. 3) / Jaccard
  *                                      ordering; pinned by Python sets and
  *                                      fractions and a hand-worked case.
@@ -233,20 +235,18 @@ static int shared(const orc_params *p)
 
 /*
  * Number of reservoirs.  Without sharing, one per bucket: L * M.  With
- * sharing, "allocated range = F * actual range": ceil(F * L * M) with F =
- * share_permille / 1000, rounded up to a multiple of 16384 (or, below that,
- * to a power of two).
+ * sharing, Sec. 3.5 defines F as the ratio of the reservoirs allocated to
+ * the range they serve; the pool serves all L tables of M buckets, so it
+ * holds ceil(F * L * M) reservoirs (at least one), F = share_permille / 1000.
  */
 uint64_t orc_pool_size(const orc_params *p)
 {
     const uint64_t M = 1ULL << (p->K * p->bits_per_hash);
     const uint64_t LM = (uint64_t)p->L * M;
-    uint64_t P, unit = 1;
+    uint64_t P;
     if (!shared(p)) return LM;
     P = (LM * (uint64_t)p->share_permille + 999) / 1000;
-    if (P < 1) P = 1;
-    while (unit < P && unit < 16384) unit <<= 1;
-    return (P + unit - 1) / unit * unit;
+    return P < 1 ? 1 : P;
 }
 
 /*

@@ -181,6 +181,55 @@ def test_rotation_densification_when_no_random_probe(orc):
             assert codes[i, j] == mins[src]
 
 
+def _probe(j, a, s_d, B):
+    h = int(fmix32_np(np.uint32(((j << 16) | a) & 0xFFFFFFFF) ^ np.uint32(s_d)))
+    return (h * B) >> 32
+
+
+def test_densification_borrows_only_from_originally_occupied_bins(orc):
+    # Sec. 2.3 uses the densification of [36]: an empty bin takes its code
+    # from the first bin of its own data-independent probe sequence that the
+    # row itself filled, never from a bin that was empty and got its code by
+    # densification.  A chained borrow (from a bin densified earlier, in
+    # either sweep order) gives another code on the bins counted below, which
+    # the rows are chosen to contain.
+    K, L, A = 4, 16, 64
+    B = K * L
+    rng = np.random.default_rng(6)
+    rows = [np.sort(rng.choice(1 << 26, size=s, replace=False)) for s in (2, 3, 4, 6, 8, 12, 20, 30)]
+    rp, ci = csr_from_rows(rows)
+    p = orc.params(K, L, 4, 8, seed=13, densify_attempts=A)
+    _, codes = orc.doph(p, rp, ci, want_codes=True)
+    s_h, s_d, _ = orc.seeds(13)
+    separating = {"ascending": 0, "descending": 0}
+    for i, r in enumerate(rows):
+        occ, mins = _raw_bins(r, B, s_h)
+        want = mins.copy()
+        first_probe = {}
+        for j in range(B):
+            if occ[j]:
+                continue
+            seq = [_probe(j, a, s_d, B) for a in range(1, A + 1)]
+            first_probe[j] = seq
+            src = next((q for q in seq if occ[q]), None)
+            if src is None:
+                src = next((j + d) % B for d in range(1, B) if occ[(j + d) % B])
+            want[j] = mins[src]
+        assert np.array_equal(codes[i], want)
+        # bins where a chained sweep would copy an already-densified bin with
+        # a different code before it reaches an originally occupied one
+        for order, before in (("ascending", lambda q, j: q < j), ("descending", lambda q, j: q > j)):
+            for j, seq in first_probe.items():
+                for q in seq:
+                    if occ[q]:
+                        break
+                    if before(q, j):
+                        if want[q] != want[j]:
+                            separating[order] += 1
+                        break
+    assert separating["ascending"] >= 20 and separating["descending"] >= 20, separating
+
+
 def test_empty_row_and_set_semantics(orc):
     rng = np.random.default_rng(4)
     base = np.sort(rng.choice(1 << 20, size=40, replace=False))
@@ -564,18 +613,24 @@ def test_sharing_off_is_the_plain_index(orc):
         assert np.array_equal(c0, c1) and np.array_equal(i0, i1)
 
 
-def test_pool_size_is_f_times_range_rounded(orc):
-    # allocated range = F * actual range, rounded up to a multiple of 16384
-    # (or, below that, to a power of two)
-    for K, L, b, permille in ((4, 64, 4, 200), (5, 32, 3, 500), (1, 2, 2, 500), (2, 3, 3, 1),
-                              (4, 16, 4, 999), (3, 5, 2, 333)):
-        LM = L << (K * b)
-        P = -(-LM * permille // 1000)
-        unit = 1
-        while unit < P and unit < 16384:
-            unit *= 2
-        want = -(-P // unit) * unit
-        assert orc.pool_size(orc.params(K, L, b, 8, share_permille=permille)) == want
+def test_pool_size_is_f_times_range(orc):
+    # Sec. 3.5: F is the ratio of the reservoirs allocated to the range they
+    # serve.  The pool serves all L tables of M = 2^(K b) buckets, so it holds
+    # the smallest whole number of reservoirs >= F * L * M; F is taken as an
+    # exact fraction here, so no float rounding can hide an off-by-one.
+    from fractions import Fraction
+    for K, L, b, permille in ((4, 64, 4, 200), (5, 32, 3, 500), (5, 32, 3, 50), (1, 2, 2, 500),
+                              (2, 3, 3, 1), (4, 16, 4, 999), (3, 5, 2, 333), (4, 16, 4, 1)):
+        F = Fraction(permille, 1000)
+        want = math.ceil(F * L * 2 ** (K * b))
+        got = orc.pool_size(orc.params(K, L, b, 8, share_permille=permille))
+        assert got == want
+        # the effective F differs from the asked one by less than one reservoir
+        assert 0 <= Fraction(got, L * 2 ** (K * b)) - F < Fraction(1, L * 2 ** (K * b))
+    # the URL-shaped index at F = 0.05: 52,429 reservoirs, not a power-of-two size
+    assert orc.pool_size(orc.params(5, 32, 3, 64, share_permille=50)) == 52429
+    # a pool never drops to zero reservoirs
+    assert orc.pool_size(orc.params(1, 1, 1, 8, share_permille=1)) == 1
 
 
 def test_reservoir_map_is_uniform_and_seeded(orc):
