@@ -67,10 +67,10 @@ extern "C" {
  * L * 2^(K * b) < 2^32, 0 <= densify_attempts <= 65535,
  * 0 <= share_permille <= 1000.
  *
- * Reservoir sharing (Sec. 3.5, "allocated range = F * actual range"): with
- * 0 < share_permille < 1000, F = share_permille / 1000 and the index has
- * P = ceil(F * L * M) reservoirs, rounded up to a multiple of 16384 (or,
- * below that, to a power of two); bucket m of table t uses reservoir
+ * Reservoir sharing (Sec. 3.5: F is the ratio of the reservoirs allocated to
+ * the bucket range they serve): with 0 < share_permille < 1000,
+ * F = share_permille / 1000 and the index has P = ceil(F * L * M)
+ * reservoirs (at least one); bucket m of table t uses reservoir
  * floor(fmix32((t * M + m) ^ s_r) * P / 2^32), a seeded random map (s_r:
  * the fourth splitmix64 output of `seed`), so buckets of any tables may share
  * one.  A reservoir keeps its R lowest-priority arrivals, with priorities
@@ -128,7 +128,7 @@ FLASH_API int flash_insert_keys(const flash_params *p, int64_t n_rows, const uin
                                 uint32_t *counts, int32_t *ids, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
-/* Adding phase from CSR: flash_hash, then flash_insert_keys.  The keys are
+/* Alg. 2 (adding phase) from CSR: flash_hash, then flash_insert_keys.  The keys are
  * written to keys_out (uint32[n_rows][L]) if it is not NULL, else kept in the
  * workspace. */
 FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t nnz,
@@ -145,8 +145,10 @@ FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t n
  * index is bit-identical (counts and occupied slots) to one
  * flash_insert_keys over all rows added, whatever the batching and order.
  * Ids must not repeat across calls (not checked).  0 <= id_base and
- * id_base + n_rows < 2^31.  Workspace: FLASH_OP_INSERT for n_rows.  Calls on
- * one index must be ordered on one stream; n_rows = 0 enqueues nothing. */
+ * id_base + n_rows <= 2^32 / 2^ceil(log2(L+2)) (the largest index the
+ * query accepts; FLASH_ENOTIMPL otherwise) and < 2^31.  Workspace:
+ * FLASH_OP_INSERT for n_rows.  Calls on one index must be ordered on one
+ * stream; n_rows = 0 enqueues nothing. */
 FLASH_API int flash_insert_keys_append(const flash_params *p, int64_t n_rows, const uint32_t *keys,
                                        int64_t id_base, uint32_t *counts, int32_t *ids,
                                        void *workspace, size_t workspace_bytes, void *stream);
@@ -163,15 +165,18 @@ FLASH_API int flash_build_index_append(const flash_params *p, int64_t n_rows, in
  * self_ids[q] (if self_ids is not NULL and the entry is >= 0) are left out.
  * out_ids / out_counts (int32[n_queries][k]) get the first k ids by (cnt
  * descending, id ascending), padded with id -1, count 0.  Requires
- * 1 <= k <= 1024, n_queries < 2^31 and fewer than 2^32 / 2^ceil(log2(L+2))
- * indexed rows (FLASH_ENOTIMPL otherwise). */
+ * 1 <= k <= 1024, n_queries < 2^31 and
+ * n_indexed <= 2^32 / 2^ceil(log2(L+2)) (FLASH_ENOTIMPL otherwise; ids and
+ * counts share one 32-bit word in the query's table).  Every id stored in
+ * the index must be < n_indexed (not checked: a larger id may be dropped or
+ * corrupted in the lists). */
 FLASH_API int flash_query_keys(const flash_params *p, const uint32_t *counts, const int32_t *ids,
                                int64_t n_indexed, int64_t n_queries, const uint32_t *qkeys,
                                const int32_t *self_ids, int32_t k, int32_t *out_ids,
                                int32_t *out_counts, void *workspace, size_t workspace_bytes,
                                void *stream);
 
-/* Querying phase from CSR queries: flash_hash of the queries into the
+/* Alg. 3 (querying phase) from CSR queries: flash_hash of the queries into the
  * workspace, then flash_query_keys. */
 FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, const int32_t *ids,
                                 int64_t n_indexed, int64_t n_queries, int64_t nnz,

@@ -53,11 +53,10 @@ int make_cfg(const flash_params* p, Cfg* c) {
   c->shared = p->share_permille > 0 && p->share_permille < 1000;
   c->P = LM;
   if (c->shared) {
-    // ceil(F * L * M), rounded up to a multiple of 16384 (or a power of two below that)
-    uint64_t P = (LM * (uint64_t)p->share_permille + 999) / 1000, unit = 1;
-    if (P < 1) P = 1;
-    while (unit < P && unit < 16384) unit <<= 1;
-    c->P = (P + unit - 1) / unit * unit;
+    // Sec. 3.5: F = allocated / served reservoirs, so the pool serving all
+    // L * M buckets holds ceil(F * L * M) of them (at least one)
+    const uint64_t P = (LM * (uint64_t)p->share_permille + 999) / 1000;
+    c->P = P < 1 ? 1 : P;
   }
   return FLASH_OK;
 }
@@ -271,6 +270,9 @@ int check_append(const Cfg& c, int64_t n_rows, int64_t id_base) {
   if (id_base < 0) return fail(FLASH_EINVAL, "id_base must be >= 0");
   if (n_rows < 0) return fail(FLASH_EINVAL, "n_rows must be >= 0");
   if (id_base + n_rows > ((int64_t)1 << 31) - 1) return fail(FLASH_EINVAL, "id_base + n_rows must be < 2^31");
+  const int cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
+  if (id_base + n_rows > ((int64_t)1 << (32 - cbits)))
+    return fail(FLASH_ENOTIMPL, "ids beyond what the query's packed (id, count) table holds");
   if ((uint64_t)n_rows * (uint64_t)c.L >= (uint64_t)1 << 32)
     return fail(FLASH_EINVAL, "n_rows * L must be < 2^32");
   return FLASH_OK;

@@ -116,6 +116,12 @@ struct PartArgs {
                            // L * row_mod entries, and entry e is row e % row_mod
 };
 
+// Buckets of the chunk starting at bucket lo: ch, or fewer in the last chunk
+// when the partition's bucket count (a shared pool) is not a multiple of ch.
+__device__ __forceinline__ uint32_t chunk_len(const PartArgs& a, uint32_t lo) {
+  return a.M - lo < a.ch ? a.M - lo : a.ch;
+}
+
 // Workgroups go to the 8 XCDs round-robin by blockIdx.x.  This bijection
 // renumbers them so that consecutive logical blocks run on one XCD: the
 // slices of one (table, chunk) then write their interleaved runs of `staged`
@@ -134,7 +140,8 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
   const uint32_t ck = (lb / a.n_slices) % a.n_chunks;
   const uint32_t t = lb / (a.n_slices * a.n_chunks);
   const uint32_t lo = ck * a.ch;
-  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads) h[j] = 0;
+  const uint32_t cl = chunk_len(a, lo);
+  for (uint32_t j = threadIdx.x; j < cl; j += kPartThreads) h[j] = 0;
   __syncthreads();
   const uint4* rowv = reinterpret_cast<const uint4*>(a.keys_t + (uint64_t)t * a.np);
   const uint32_t v0 = sl * a.slice_vecs;
@@ -143,14 +150,14 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
   for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
     const uint4 x = rowv[v];
     const uint32_t d0 = x.x - lo, d1 = x.y - lo, d2 = x.z - lo, d3 = x.w - lo;
-    if (d0 < a.ch) atomicAdd(&h[d0], 1u);
-    if (d1 < a.ch) atomicAdd(&h[d1], 1u);
-    if (d2 < a.ch) atomicAdd(&h[d2], 1u);
-    if (d3 < a.ch) atomicAdd(&h[d3], 1u);
+    if (d0 < cl) atomicAdd(&h[d0], 1u);
+    if (d1 < cl) atomicAdd(&h[d1], 1u);
+    if (d2 < cl) atomicAdd(&h[d2], 1u);
+    if (d3 < cl) atomicAdd(&h[d3], 1u);
   }
   __syncthreads();
   const uint64_t b0 = (uint64_t)t * a.M + lo;
-  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads)
+  for (uint32_t j = threadIdx.x; j < cl; j += kPartThreads)
     a.part[(b0 + j) * a.n_slices + sl] = h[j];
 }
 
@@ -163,8 +170,9 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) 
   const uint32_t ck = (lb / a.n_slices) % a.n_chunks;
   const uint32_t t = lb / (a.n_slices * a.n_chunks);
   const uint32_t lo = ck * a.ch;
+  const uint32_t cl = chunk_len(a, lo);
   const uint64_t b0 = (uint64_t)t * a.M + lo;
-  for (uint32_t j = threadIdx.x; j < a.ch; j += kPartThreads)
+  for (uint32_t j = threadIdx.x; j < cl; j += kPartThreads)
     cur[j] = a.partoff[(b0 + j) * a.n_slices + sl];
   __syncthreads();
   const uint4* rowv = reinterpret_cast<const uint4*>(a.keys_t + (uint64_t)t * a.np);
@@ -178,7 +186,7 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const uint32_t d = kk[j] - lo;
-      if (d < a.ch) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + row0 + (uint32_t)j);
+      if (d < cl) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + row0 + (uint32_t)j);
     }
   }
 }
@@ -485,7 +493,7 @@ Geo geometry(const Cfg& c, int64_t n_rows) {
   g.Mp = c.shared ? c.P : (uint64_t)c.M;
   g.np_part = c.shared ? g.np * (uint32_t)c.L : g.np;
   g.ch = g.Mp < kChunk ? (uint32_t)g.Mp : kChunk;
-  g.n_chunks = (uint32_t)(g.Mp / g.ch);
+  g.n_chunks = (uint32_t)((g.Mp + g.ch - 1) / g.ch);  // a shared pool may end in a short chunk
   const uint32_t base_blocks = g.Lp * g.n_chunks;
   // about one partition block per CU: more row slices interleave more runs
   // of `staged` (partial-line writes), fewer leave CUs idle

@@ -475,25 +475,36 @@ def test_query_batch_from_csr(fl, orc):
     assert np.array_equal(i32(oi).reshape(q, 25), wi) and np.array_equal(i32(oc).reshape(q, 25), wc)
 
 
-def test_url_shaped_graph(fl, orc):
-    # several hundred thousand rows, B = 160 (not a power of two), many
-    # saturated buckets (load above R)
+def test_url_full_size_graph(fl, orc):
+    # The URL-shaped graph at full size: 2.4M rows, B = 160 (not a power of
+    # two), 73 arrivals per bucket against R = 64, so most buckets are full
+    # and the query runs its full-bucket stage layout.  Keys, tables and all
+    # 2.4M k-NN lists against the oracle.
+    import torch
     from paper_1709_01190_amd import datagen
-    say("url-shaped 300k graph")
-    spec = datagen.scaled(datagen.URL, 300_000)
+    say("url-shaped full size graph")
+    spec = datagen.URL
     rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
+    n = spec.n_rows
+    K, L, b, R, k = 5, 32, 3, 64, 64
+    p = fl.flash_params.make(K, L, b, R, seed=1)
+    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
+    gkeys = torch.empty(n * L, dtype=torch.int32, device="cuda")
+    fl.flash_hash(p, rp_d, ci_d, gkeys)
+    torch.cuda.synchronize()
     rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
-    p = fl.flash_params.make(5, 32, 3, 64, seed=1)
-    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, 64)
-    okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(5, 32, 3, 64, seed=1), rp, ci, 64)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 32, 1 << 15, 64)
-    assert np.array_equal(i32(oi), wi) and np.array_equal(i32(oc), wc)
+    del rp_d, ci_d
+    okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(K, L, b, R, seed=1), rp, ci, k)
+    assert np.array_equal(u32(gkeys).reshape(n, L), okeys)
+    occ = np.minimum(ocounts, R)
+    assert occ.mean() > 0.6 * R, "the full-bucket regime is not reached"
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
+    assert np.array_equal(i32(oi).reshape(n, k), wi) and np.array_equal(i32(oc).reshape(n, k), wc)
 
 
 def test_webspam_full_size_graph(fl, orc):
     # The benchmark's workload and launch shape: 350,000 rows, ~1.3G nonzeros.
-    # Tables are compared in full; k-NN lists on 3,000 sampled queries (the
-    # oracle answers them one by one against its own full index).
+    # Keys, tables and all 350,000 k-NN lists against the oracle.
     import torch
     from paper_1709_01190_amd import datagen
     say("webspam-shaped full size graph")
@@ -513,12 +524,8 @@ def test_webspam_full_size_graph(fl, orc):
     assert np.array_equal(u32(gkeys).reshape(n, L), okeys)
     ocounts, oids = orc.build_tables(op, okeys)
     occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
-    rng = np.random.default_rng(77)
-    sample = np.sort(rng.choice(n, size=3000, replace=False))
-    wi, wc = orc.query(op, ocounts, oids, okeys[sample], k, self_ids=sample.astype(np.int32))
-    gi = i32(oi)[sample]
-    gc = i32(oc)[sample]
-    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+    wi, wc = orc.query(op, ocounts, oids, okeys, k, self_ids=np.arange(n, dtype=np.int32))
+    assert np.array_equal(i32(oi).reshape(n, k), wi) and np.array_equal(i32(oc).reshape(n, k), wc)
 
 
 def test_query_mixed_k(fl, orc, tiny_index):
@@ -650,7 +657,8 @@ def test_autotune_query_batch(fl, orc, saturated_index, tuned):
 def test_clicklog_full_size_uneven(fl, orc):
     # The uneven-batch workload at full size: a 40M-row click-log-shaped
     # index (K=4, L=32, b=4, R=256; most reservoirs full) compared in full
-    # with the oracle's, and 2,000 heavy-tailed queries with mixed k.
+    # with the oracle's, and 100,000 heavy-tailed queries with mixed k (every
+    # one of them compared, the few hundred above 1,000 nonzeros included).
     import torch
     from paper_1709_01190_amd import datagen
     say("click-log full size index + uneven queries")
@@ -663,7 +671,10 @@ def test_clicklog_full_size_uneven(fl, orc):
     fl.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
     torch.cuda.synchronize()
     del ws
-    qrp_d, qci_d, kq = _uneven_queries(spec, 2000)
+    nq = 100_000
+    qrp_d, qci_d, kq = _uneven_queries(spec, nq)
+    sizes = (qrp_d[1:] - qrp_d[:-1]).cpu().numpy()
+    assert (sizes > 1000).sum() >= 100 and sizes.max() > 10_000   # the tail is present
     gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
     op = orc.params(K, L, b, R, seed=1)
     okeys = orc.doph(op, rp_d.cpu().numpy(), ci_d.cpu().numpy())
@@ -893,6 +904,31 @@ def test_shared_heavy_reservoirs(fl, orc, R):
     q = 500
     wi, wc = orc.query(op, ocounts, oids, keys[:q], 40, self_ids=np.arange(q, dtype=np.int32))
     gi, gc = gpu_query(fl, p, counts, ids, n, keys[:q], 40, np.arange(q, dtype=np.int32))
+    assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
+
+
+@pytest.mark.parametrize("K,L,b,R,permille", [(5, 32, 3, 64, 50), (5, 32, 3, 64, 999), (4, 64, 4, 128, 7),
+                                               (1, 2, 2, 8, 1), (1, 2, 2, 8, 300), (2, 3, 3, 16, 17)])
+def test_shared_pool_of_any_size(fl, orc, K, L, b, R, permille):
+    # pools of exactly ceil(F * L * M) reservoirs: several partition chunks of
+    # 16,384 and a short last one (52,429 = 3 * 16,384 + 3,277 for the
+    # URL-shaped parameters at F = 0.05), one short chunk (F = 0.999), and
+    # pools of 1, 3 and 4 reservoirs
+    say("shared pool", K, L, b, R, permille)
+    rng = np.random.default_rng(1000 + permille)
+    n = 60_000
+    keys = rng.integers(0, 1 << (K * b), size=(n, L), dtype=np.int64).astype(np.uint32)
+    keys[rng.random((n, L)) < 0.01] = EMPTY
+    p, op, P = _shared_pair(fl, orc, K, L, b, R, 3, permille)
+    LM = L << (K * b)
+    assert P == max(1, -(-LM * permille // 1000))
+    ocounts, oids = orc.build_tables(op, keys)
+    counts, ids = gpu_insert(fl, p, keys)
+    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
+    q = 2000
+    k = min(64, L * R)
+    wi, wc = orc.query(op, ocounts, oids, keys[:q], k, self_ids=np.arange(q, dtype=np.int32))
+    gi, gc = gpu_query(fl, p, counts, ids, n, keys[:q], k, np.arange(q, dtype=np.int32))
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
 
 

@@ -135,6 +135,11 @@ def test_append_arguments_are_checked_on_the_host(fl):
         r = L.flash_insert_keys_append(ctypes.byref(p), n, ctypes.c_void_p(16), base, ctypes.c_void_p(16),
                                        ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
         assert r == fl.FLASH_EINVAL
+    # ids past what a query can hold in its packed (id, count) words: L = 16
+    # leaves 27 id bits
+    r = L.flash_insert_keys_append(ctypes.byref(p), 10, ctypes.c_void_p(16), (1 << 27) - 5, ctypes.c_void_p(16),
+                                   ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+    assert r == fl.FLASH_ENOTIMPL
     # too small a workspace
     r = L.flash_insert_keys_append(ctypes.byref(p), 1000, ctypes.c_void_p(16), 0, ctypes.c_void_p(16),
                                    ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None)

@@ -136,37 +136,51 @@ def test_burst_and_batch_all_agree(orc, small_index):
 
 @pytest.mark.gpu
 def test_gpu_continuous_serving_equals_alone(orc):
+    # The serving workload's index: the full 2.4M-row URL-shaped index.  240
+    # requests of 1..4,096 queries with k in {10, 50, 200} go through the
+    # continuous server on several streams at once; each request's lists
+    # must equal the same request run alone and the oracle's.
     import torch
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1709_01190_amd import datagen, flash
-    print("[case] gpu serving identity", flush=True)
-    spec = datagen.scaled(datagen.URL, 100_000)
-    rp, ci = datagen.make_rows(spec, 1)
+    print("[case] gpu serving identity on the full URL-shaped index", flush=True)
+    spec = datagen.URL
+    rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
     counts, ids = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
-    flash.flash_build_index(p, rp.cuda(), ci.cuda(), counts, ids, ws)
+    flash.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
     torch.cuda.synchronize()
-    qspec = datagen.scaled(datagen.URL, 200_000)
+    rp, ci = rp_d.cpu(), ci_d.cpu()
+    del ws, rp_d, ci_d
+
+    # query rows from the index's clusters (drawn with seed 2); a request
+    # takes a random slice of the pool
+    import dataclasses
+    pool_n = 150_000
+    qrp, qci = (a.cpu().numpy() for a in datagen.make_rows(dataclasses.replace(spec, n_rows=pool_n), 1,
+                                                           device="cuda", row_seed=2))
 
     def rows(n, seed):
-        a, b = datagen.make_rows(datagen.scaled(qspec, n), seed)
-        return a.numpy(), b.numpy()
-    reqs = serving.make_requests(rows, 60, qps=5e5, seed=11, max_batch=512)
+        st = np.random.default_rng(seed).integers(0, pool_n - n + 1)
+        a, b = int(qrp[st]), int(qrp[st + n])
+        return (qrp[st:st + n + 1] - a).astype(np.int64), qci[a:b].copy()
+    reqs = serving.make_requests(rows, 240, qps=2e6, seed=11, max_batch=4096)
+    assert {r.k for r in reqs} == {10, 50, 200}
     ex = serving.GpuExecutor(p, counts, ids, spec.n_rows)
-    stats = serving.ContinuousServer(ex, budget_bytes=256 << 20, slots=6).run(reqs)
-    assert stats["requests"] == 60
+    stats = serving.ContinuousServer(ex, budget_bytes=1 << 30, slots=8).run(reqs)
+    assert stats["requests"] == 240 and stats["rejected"] == 0
     # each result is the same as the request run alone, and as the oracle
     op = orc.params(5, 32, 3, 64, seed=1)
     okeys = orc.doph(op, rp.numpy(), ci.numpy())
     ocounts, oids = orc.build_tables(op, okeys)
+    del okeys
     slot = ex.new_slot()
     for r in reqs:
         ex.launch(slot, r.row_ptr, r.col_idx, r.k)
         torch.cuda.synchronize()
         ai, ac = ex.result(slot, r.n, r.k)
         assert np.array_equal(r.out_ids, ai) and np.array_equal(r.out_counts, ac)
-    for r in reqs[:10]:
         wi, wc = orc.query(op, ocounts, oids, orc.doph(op, r.row_ptr, r.col_idx), r.k)
         assert np.array_equal(r.out_ids, wi) and np.array_equal(r.out_counts, wc)
