@@ -49,15 +49,18 @@ def main():
     ap.add_argument("--batches", type=int, default=24, help="append: batches the index is grown in")
     ap.add_argument("--rates", default="5e4,2e5,5e5,1e6,2e6",
                     help="serving: offered queries per second, comma separated")
-    ap.add_argument("--requests", type=int, default=5000, help="serving: requests per rate")
+    ap.add_argument("--requests", type=int, default=20000, help="serving: requests per rate and repeat")
+    ap.add_argument("--serving-warmup", type=int, default=2000, help="serving: untimed requests per rate")
+    ap.add_argument("--serving-repeats", type=int, default=3, help="serving: timed runs per rate")
+    ap.add_argument("--serving-leg", default="1e6,2e6",
+                    help="graph workloads: offered rates of the short serving leg on the URL-shaped "
+                         "index (2,000 requests each, after 300 untimed); empty skips it")
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight at once (streams)")
-    ap.add_argument("--recall-queries", type=int, default=1000,
+    ap.add_argument("--recall-queries", type=int, default=None,
                     help="sampled queries (graph workloads: rows) scored against brute-force "
                          "exact Jaccard; 0 skips it")
     ap.add_argument("--rows", type=int, default=0, help="override the row count (parity/debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-queries", type=int, default=20000,
-                    help="queries the CPU oracle answers (the rest is extrapolated)")
     ap.add_argument("--traffic-table", default=os.path.join(ROOT, "profiles", "hbm_traffic.txt"),
                     help="calibrated per-launch HBM bytes from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--copy-reps", type=int, default=1,
@@ -67,6 +70,8 @@ def main():
                     help="instead of the benchmark, copy this many MiB device to device (a plain "
                          "copy kernel of known size that calibrates the HBM byte counters)")
     args = ap.parse_args()
+    if args.recall_queries is None:   # the serving workload scores 10,000 sampled queries
+        args.recall_queries = 10_000 if args.workload == "serving" else 1000
     if args.copy_mib:
         copy_calibration(args.copy_mib, args.copy_reps)
         return
@@ -162,10 +167,10 @@ def main():
         f"hash {ph[0]:.3f} insert {ph[1]:.3f} query {ph[2]:.3f} ms")
 
     # algorithmic bytes per launch
-    kq = keys.view(n, L).long()
+    kq = keys.view(n, L).long() & 0xFFFFFFFF
     cnt = counts.view(L, M).long()
     occ = torch.clamp(cnt[torch.arange(L, device="cuda")[None, :], kq.clamp(0, M - 1)], max=R)
-    occ = torch.where(kq >= 0, occ, torch.zeros_like(occ)) if kq.min() < 0 else occ
+    occ = torch.where(kq < M, occ, torch.zeros_like(occ))   # empty rows' keys hit no bucket
     occ_sum = int(occ.sum().item())
     per_q = occ.sum(dim=1).float()
     qs = torch.quantile(per_q[:min(n, 1 << 20)], torch.tensor([0.5, 0.9, 0.99, 1.0], device="cuda"))
@@ -173,10 +178,12 @@ def main():
         % (per_q.mean().item(), *qs.tolist(), (per_q > 1024).float().mean().item(),
            (per_q > 2048).float().mean().item()))
     bytes_hash = 4 * nnz + 8 * (n + 1) + 4 * n * L
-    n_ins = n * L
+    # insert: read the keys (4 B per insertion), stage an (id, priority)
+    # pair per insertion (12 B), write the counts (4 B per bucket) and the
+    # kept ids (4 B per occupied slot)
+    n_ins = int((kq < M).sum().item())
     nb = L * M
-    bytes_insert = (4 * n_ins * 2 + 4 * n_ins * 3 + 4 * n_ins + 4 * nb * 4
-                    + 4 * int(torch.clamp(cnt, max=R).sum().item()))
+    bytes_insert = 4 * n * L + 12 * n_ins + 4 * nb + 4 * int(torch.clamp(cnt, max=R).sum().item())
     bytes_query = 4 * n * L * 2 + 4 * occ_sum + 8 * n * k + 4 * n
     phases = {
         "hash": {"ms": round(float(ph[0]), 4), "alg_bytes": bytes_hash,
@@ -205,9 +212,26 @@ def main():
                                       q_rows=sel)
         log(f"R@{k} over {len(sel)} sampled rows: {recall} ({time.time() - t1:.1f}s)")
 
+    serving_leg = None
+    if args.serving_leg and args.workload == "webspam":
+        env = _url_serving_setup()
+        rates = [float(x) for x in args.serving_leg.split(",")]
+        table = _serving_rates(env, rates, 2000, 300, 1, args.slots, 4 << 30)
+        serving_leg = {"workload": "url-shaped serving (2.4M-row index; batches of 1..4096 queries, "
+                                   "k in {10, 50, 200}, Poisson arrivals)",
+                       "requests_per_rate": 2000, "warmup_requests": 300, "slots": args.slots,
+                       "rates": [{"offered_qps": r["offered_qps"],
+                                  "continuous": {x: r["continuous"][x] for x in ("p50_ms", "p99_ms", "qps")},
+                                  "batch_all": {x: r["batch_all"][x] for x in ("p50_ms", "p99_ms", "qps")},
+                                  "identical_lists": r["identical_lists"],
+                                  "buffer_grows_timed": r["repeats"][0]["buffer_grows_timed"]}
+                                 for r in table]}
+        del env
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(rp, ci, K, L, b, R, k, n, args.cpu_queries)
+        cpu = cpu_baseline(rp, ci, K, L, b, R, k, n)
 
     out = {
         "metric": f"k-NN graph build time + queries/s ({args.workload}-shape)",
@@ -229,22 +253,25 @@ def main():
         "phases": phases,
         "graph_ms_per_step": round(graph_ms, 4),
         "recall": recall,
+        "serving": serving_leg,
     }
     print(json.dumps(out), flush=True)
 
 
-def serving_bench(args):
-    """p50/p99 latency and throughput of the continuous-batching server against
-    plain batch-all, on a resident URL-shaped index (2.4M rows; K=5 L=32 b=3
-    R=64), with Poisson arrivals of batches of 1..4096 URL-shaped queries and
-    k in {10, 50, 200}."""
+def _url_serving_setup(rows_override=0, pool_n=400_000):
+    """The serving workload's resident index (URL-shaped, 2.4M rows; K=5 L=32
+    b=3 R=64) and a pool of query rows from its clusters (rows drawn with seed
+    2); a request of n queries takes a random slice of n pool rows."""
+    import dataclasses
+
     import numpy as np
     import torch
 
-    from paper_1709_01190_amd import datagen, flash, serving
+    from paper_1709_01190_amd import datagen, flash
 
-    torch.cuda.set_device(0)
     spec = datagen.URL
+    if rows_override:
+        spec = datagen.scaled(spec, rows_override)
     t0 = time.time()
     rp, ci = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
@@ -254,10 +281,6 @@ def serving_bench(args):
     torch.cuda.synchronize()
     del ws
     log(f"url-shaped index: {spec.n_rows} rows, {int(ci.numel())} nnz, built in {time.time() - t0:.1f}s")
-    # a pool of query rows from the index's clusters (rows drawn with seed 2);
-    # each request takes a random slice of it
-    import dataclasses
-    pool_n = 400_000
     qrp_d, qci_d = datagen.make_rows(dataclasses.replace(spec, n_rows=pool_n), 1, device="cuda", row_seed=2)
     qrp, qci = qrp_d.cpu().numpy(), qci_d.cpu().numpy()
     del qrp_d, qci_d
@@ -267,31 +290,86 @@ def serving_bench(args):
         a, b = int(qrp[st]), int(qrp[st + n])
         return (qrp[st:st + n + 1] - a).astype(np.int64), qci[a:b].copy()
 
-    ex = serving.GpuExecutor(p, counts, ids, spec.n_rows)
-    budget = 4 << 30
-    cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=args.slots)
+    return {"spec": spec, "p": p, "counts": counts, "ids": ids, "rp": rp, "ci": ci,
+            "rows": rows, "qrp": qrp, "qci": qci, "pool_n": pool_n}
+
+
+def _serving_rates(env, rates, n_requests, warmup, repeats, slots, budget):
+    """Continuous batching against batch-all at each offered rate: `warmup`
+    untimed requests at that rate through both servers, then `repeats` timed
+    runs of `n_requests` each (fresh arrivals per repeat, the same for both
+    servers).  Every continuous slot is sized beforehand for the largest
+    request and batch-all's slot for 64K queries, so that no timed request
+    allocates; the number of buffer growths inside the timed runs is
+    reported (0 expected)."""
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import serving
+
+    rows = env["rows"]
+    ex = serving.GpuExecutor(env["p"], env["counts"], env["ids"], env["spec"].n_rows)
+    cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=slots)
     batch = serving.BatchAllServer(ex, budget_bytes=budget)
-    warm = serving.make_requests(rows, 50, qps=5e5, seed=99)
-    cont.run(warm)
-    batch.run(serving.make_requests(rows, 50, qps=5e5, seed=99))
-    torch.cuda.synchronize()
+    max_batch = 4096
+    cont.reserve([serving.Request(0, 0.0, np.zeros(max_batch + 1, np.int64), np.zeros(max_batch * 2000, np.int32),
+                                  200)])
+    batch.reserve(65536, 65536 * 200, 200)
     table = []
-    for rate in [float(x) for x in args.rates.split(",")]:
-        reqs = serving.make_requests(rows, args.requests, qps=rate, seed=int(rate) % 100_003)
-        c = cont.run(reqs)
-        c_lists = [(r.out_ids, r.out_counts) for r in reqs]
-        reqs2 = serving.make_requests(rows, args.requests, qps=rate, seed=int(rate) % 100_003)
-        b = batch.run(reqs2)
-        same = all(np.array_equal(x[0], r.out_ids) and np.array_equal(x[1], r.out_counts)
-                   for x, r in zip(c_lists, reqs2) if not r.rejected)
-        row = {"offered_qps": rate, "continuous": {k2: round(v, 3) for k2, v in c.items()},
-               "batch_all": {k2: round(v, 3) for k2, v in b.items()}, "identical_lists": bool(same)}
-        log(json.dumps(row))
+    for rate in rates:
+        seed0 = int(rate) % 100_003
+        if warmup:
+            cont.run(serving.make_requests(rows, warmup, qps=rate, seed=seed0 + 7919))
+            batch.run(serving.make_requests(rows, warmup, qps=rate, seed=seed0 + 7919))
+            torch.cuda.synchronize()
+        reps = []
+        for rep in range(repeats):
+            g0 = ex.grows
+            reqs = serving.make_requests(rows, n_requests, qps=rate, seed=seed0 + 104_729 * rep)
+            c = cont.run(reqs)
+            c_lists = [(r.out_ids, r.out_counts) for r in reqs]
+            reqs2 = serving.make_requests(rows, n_requests, qps=rate, seed=seed0 + 104_729 * rep)
+            b = batch.run(reqs2)
+            same = all(np.array_equal(x[0], r.out_ids) and np.array_equal(x[1], r.out_counts)
+                       for x, r in zip(c_lists, reqs2) if not r.rejected)
+            reps.append({"continuous": {k2: round(v, 3) for k2, v in c.items()},
+                         "batch_all": {k2: round(v, 3) for k2, v in b.items()},
+                         "identical_lists": bool(same), "buffer_grows_timed": ex.grows - g0})
+            log(json.dumps({"offered_qps": rate, "repeat": rep, **reps[-1]}))
+        row = {"offered_qps": rate, "repeats": reps}
+        for side in ("continuous", "batch_all"):
+            for key in ("p50_ms", "p99_ms", "qps"):
+                vals = [r[side][key] for r in reps]
+                row.setdefault(side, {})[key] = round(float(np.median(vals)), 3)
+                row[side][key + "_range"] = [round(min(vals), 3), round(max(vals), 3)]
+        row["continuous_p99_wins"] = sum(r["continuous"]["p99_ms"] <= r["batch_all"]["p99_ms"] for r in reps)
+        row["identical_lists"] = all(r["identical_lists"] for r in reps)
         table.append(row)
+    return table
+
+
+def serving_bench(args):
+    """p50/p99 latency and throughput of the continuous-batching server against
+    plain batch-all, on a resident URL-shaped index (2.4M rows; K=5 L=32 b=3
+    R=64), with Poisson arrivals of batches of 1..4096 URL-shaped queries and
+    k in {10, 50, 200}; R@50 of sampled queries against brute-force Jaccard."""
+    import numpy as np
+    import torch
+
+    from paper_1709_01190_amd import flash
+
+    torch.cuda.set_device(0)
+    env = _url_serving_setup(args.rows)
+    spec, p, counts, ids = env["spec"], env["p"], env["counts"], env["ids"]
+    budget = 4 << 30
+    rates = [float(x) for x in args.rates.split(",")]
+    table = _serving_rates(env, rates, args.requests, args.serving_warmup, args.serving_repeats,
+                           args.slots, budget)
     recall = None
     if args.recall_queries > 0:
+        qrp, qci, pool_n = env["qrp"], env["qci"], env["pool_n"]
         rng = np.random.default_rng(3)
-        sel = np.sort(rng.choice(pool_n, size=args.recall_queries, replace=False))
+        sel = np.sort(rng.choice(pool_n, size=min(args.recall_queries, pool_n), replace=False))
         k = 50
         srp = np.concatenate([[0], np.cumsum(qrp[sel + 1] - qrp[sel])]).astype(np.int64)
         sci = np.concatenate([qci[qrp[i]:qrp[i + 1]] for i in sel]).astype(np.int32)
@@ -301,8 +379,9 @@ def serving_bench(args):
         qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=len(sel), k=k)
         flash.flash_query_batch(p, counts, ids, spec.n_rows, srp_d, sci_d, k, oi, oc, qws)
         torch.cuda.synchronize()
-        recall = recall_exact_jaccard(rp, ci, spec.n_cols, srp_d, sci_d, oi.view(len(sel), k))
-        log(f"R@{k} over {len(sel)} sampled queries: {recall}")
+        t1 = time.time()
+        recall = recall_exact_jaccard(env["rp"], env["ci"], spec.n_cols, srp_d, sci_d, oi.view(len(sel), k))
+        log(f"R@{k} over {len(sel)} sampled queries: {recall} ({time.time() - t1:.1f}s)")
     top = max(table, key=lambda r: r["offered_qps"]) if table else None
     out = {
         "metric": "serving p99 latency (url-shape index, continuous batching)",
@@ -315,7 +394,8 @@ def serving_bench(args):
         "data": "synthetic",
         "config": {"workload": "url-shaped serving", "index_rows": spec.n_rows, "K": 5, "L": 32,
                    "bits_per_hash": 3, "R": 64, "k": [10, 50, 200], "batch": [1, 4096],
-                   "requests_per_rate": args.requests, "hbm_budget_bytes": budget, "slots": args.slots},
+                   "requests_per_rate": args.requests, "warmup_requests": args.serving_warmup,
+                   "repeats": args.serving_repeats, "hbm_budget_bytes": budget, "slots": args.slots},
         "rates": table,
         "recall": recall,
     }
@@ -815,31 +895,67 @@ def _kernel_source_sha():
     return h.hexdigest()[:16]
 
 
-def cpu_baseline(rp, ci, K, L, b, R, k, n, q_sample):
-    """The CPU oracle (plain C + OpenMP) on the same arrays: hash and build of
-    all rows, then q_sample of the n queries; the query time is scaled to n."""
+def _host_cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(rp, ci, K, L, b, R, k, n, reps=3):
+    """The CPU oracle (plain C + OpenMP over rows, queries and tables), built
+    here with gcc -O3 -march=native for this host, on the same arrays: the
+    whole k-NN graph (hash, build and all n queries, self left out), the
+    median of `reps` runs on all host threads.  Also the tiny 10,000-row
+    graph on one thread.  Input copies to the host are outside the timing."""
+    import tempfile
+
     import numpy as np
 
     import oracle
+    from paper_1709_01190_amd import datagen
 
+    so = os.path.join(tempfile.mkdtemp(prefix="flash_oracle_native_"), "liboracle_native.so")
+    oracle.build(force=True, out=so, opt=oracle.NATIVE_FLAGS)
+    os.environ["FLASH_ORACLE_LIB"] = so   # read by oracle.lib() on its first call
     rph, cih = rp.cpu().numpy(), ci.cpu().numpy()
     op = oracle.params(K, L, b, R, seed=1)
+    runs = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        keys = oracle.doph(op, rph, cih)
+        t1 = time.perf_counter()
+        counts, ids = oracle.build_tables(op, keys)
+        t2 = time.perf_counter()
+        oracle.query(op, counts, ids, keys, k, self_ids=np.arange(n, dtype=np.int32))
+        t3 = time.perf_counter()
+        runs.append((t3 - t0, t1 - t0, t2 - t1, t3 - t2))
+        del keys, counts, ids
+    runs.sort()
+    total, th, tb, tq = runs[len(runs) // 2]
+    threads = oracle.num_threads()
+    log(f"cpu oracle ({threads} threads, -O3 -march=native): hash {th:.2f}s build {tb:.2f}s "
+        f"query {tq:.2f}s -> {total:.2f}s for the graph (median of {reps})")
+    # one thread, the tiny graph (10,000 rows; K=4 L=16 b=4 R=32 k=16)
+    trp, tci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
+    oracle.set_num_threads(1)
     t0 = time.perf_counter()
-    keys = oracle.doph(op, rph, cih)
-    t1 = time.perf_counter()
-    counts, ids = oracle.build_tables(op, keys)
-    t2 = time.perf_counter()
-    qs = min(n, q_sample)
-    sel = np.arange(qs, dtype=np.int64)
-    oracle.query(op, counts, ids, keys[sel], k, self_ids=sel.astype(np.int32))
-    t3 = time.perf_counter()
-    total = (t1 - t0) + (t2 - t1) + (t3 - t2) * n / qs
-    log(f"cpu oracle: hash {t1 - t0:.2f}s build {t2 - t1:.2f}s query({qs}) {t3 - t2:.2f}s "
-        f"-> {total:.2f}s for the graph")
-    return {"value": round(n / total, 1), "unit": "queries/s", "cores": oracle.num_threads(),
+    oracle.knn_graph(oracle.params(4, 16, 4, 32, seed=1), trp, tci, 16)
+    t_tiny = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    log(f"cpu oracle, one thread: tiny graph {t_tiny:.3f}s")
+    return {"value": round(n / total, 1), "unit": "queries/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"hash+build of all {n} rows, {qs} of {n} queries timed and scaled to {n}",
-            "seconds_graph": round(total, 3)}
+            "sample": f"the whole graph (hash + build of all {n} rows, all {n} queries), median of {reps}",
+            "seconds_graph": round(total, 3),
+            "phases_s": {"hash": round(th, 3), "build": round(tb, 3), "query": round(tq, 3)},
+            "build_flags": " ".join(oracle.NATIVE_FLAGS),
+            "host_cpu": _host_cpu_model(),
+            "one_thread_tiny_graph_s": round(t_tiny, 4)}
 
 
 if __name__ == "__main__":

@@ -35,14 +35,22 @@ class Params(ctypes.Structure):
                 ("share_permille", ctypes.c_int32)]
 
 
-def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (OpenMP, -O2) into oracle/liboracle.so."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
-        tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-std=gnu99", "-fopenmp", "-fPIC", "-shared",
+# gcc flags of the checker build (portable: the same .so runs on any x86-64
+# host) and of the timing build, which targets the host it is compiled on
+CHECK_FLAGS = ["-O2"]
+NATIVE_FLAGS = ["-O3", "-march=native"]
+
+
+def build(force: bool = True, out: str = _LIB, opt=None) -> str:
+    """Compile the oracle with gcc (OpenMP; CHECK_FLAGS unless `opt` names
+    others) into `out` (default oracle/liboracle.so)."""
+    if force or not os.path.exists(out) or os.path.getmtime(out) < os.path.getmtime(_SRC):
+        tmp = out + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc"] + list(opt or CHECK_FLAGS) +
+                              ["-std=gnu99", "-fopenmp", "-fPIC", "-shared",
                                "-Wall", "-Wno-unknown-pragmas", _SRC, "-o", tmp])
-        os.replace(tmp, _LIB)
-    return _LIB
+        os.replace(tmp, out)
+    return out
 
 
 _lib = None
@@ -89,6 +97,8 @@ def lib():
         L.orc_rerank.argtypes = [ctypes.c_int, P, P, ctypes.c_int64, P, P, P, ctypes.c_int32,
                                  ctypes.c_int32, P, P]
         L.orc_num_threads.restype = ctypes.c_int
+        L.orc_set_num_threads.restype = None
+        L.orc_set_num_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
@@ -131,6 +141,11 @@ def fmix32(x: int) -> int:
 
 def priority(s_p: int, t: int, i: int) -> int:
     return lib().orc_priority(s_p, t, i)
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's parallel loops from now on (timing only)."""
+    lib().orc_set_num_threads(int(n))
 
 
 def num_threads() -> int:

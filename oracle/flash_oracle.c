@@ -701,3 +701,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads the parallel loops use from now on (n >= 1); for timing only. */
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

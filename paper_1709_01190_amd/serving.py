@@ -87,6 +87,7 @@ class GpuExecutor:
         self._torch, self._flash = torch, flash
         self.p, self.counts, self.ids, self.n_indexed = p, counts, ids, n_indexed
         self.device = torch.device(device)
+        self.grows = 0   # buffers allocated or grown so far (a timed run should add none)
 
     def bytes_for(self, n: int, nnz: int, k: int) -> int:
         """Device memory one request holds while in flight."""
@@ -111,7 +112,24 @@ class GpuExecutor:
             t = (torch.empty(cap, dtype=dtype, pin_memory=True) if pinned
                  else torch.empty(cap, dtype=dtype, device=self.device))
             slot["bufs"][name] = t
+            self.grows += 1
         return t[:numel]
+
+    def reserve(self, slot, n: int, nnz: int, k: int) -> None:
+        """Grows the slot's buffers now to what a request of n queries, nnz
+        columns and this k needs, so that no request up to that size
+        allocates or pins memory while it is being timed."""
+        torch, flash = self._torch, self._flash
+        i64, i32, u8 = torch.int64, torch.int32, torch.uint8
+        wsb = flash.flash_workspace_bytes(flash.OP_QUERY, self.p, n_queries=n, k=k)
+        with torch.cuda.stream(slot["stream"]):   # device buffers belong to the slot's stream
+            for name, numel, dtype, pinned in (("rp_h", n + 1, i64, True), ("ci_h", nnz, i32, True),
+                                               ("rp_d", n + 1, i64, False), ("ci_d", nnz, i32, False),
+                                               ("oi", n * k, i32, False), ("oc", n * k, i32, False),
+                                               ("ws", wsb, u8, False), ("oi_h", n * k, i32, True),
+                                               ("oc_h", n * k, i32, True)):
+                self._buf(slot, name, numel, dtype, pinned)
+        torch.cuda.synchronize(self.device)
 
     def launch(self, slot, row_ptr: np.ndarray, col_idx: np.ndarray, k: int) -> None:
         torch, flash = self._torch, self._flash
@@ -153,6 +171,11 @@ class GpuExecutor:
 
 # ---------------------------------------------------------------- servers
 
+def _reserve(executor, slot, n: int, nnz: int, k: int) -> None:
+    if hasattr(executor, "reserve"):
+        executor.reserve(slot, n, nnz, k)
+
+
 class ContinuousServer:
     """Continuous batching: admit by arrival, a free slot and the HBM budget."""
 
@@ -160,6 +183,18 @@ class ContinuousServer:
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slots = [executor.new_slot() for _ in range(slots)]
+
+    def reserve(self, requests: List[Request]) -> None:
+        """Sizes every slot for the largest of these requests (queries,
+        columns and outputs taken separately), so that none of them
+        allocates while it is timed."""
+        if not requests:
+            return
+        n = max(r.n for r in requests)
+        nnz = max(r.nnz for r in requests)
+        k = max(r.k for r in requests)
+        for slot in self.slots:
+            _reserve(self.ex, slot, n, nnz, k)
 
     def run(self, requests: List[Request], clock=time.perf_counter) -> Dict:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
@@ -210,6 +245,10 @@ class BatchAllServer:
         self.ex = executor
         self.budget = int(budget_bytes)
         self.slot = executor.new_slot()
+
+    def reserve(self, n: int, nnz: int, k: int) -> None:
+        """Sizes the one slot for a batch of n queries, nnz columns and k."""
+        _reserve(self.ex, self.slot, n, nnz, k)
 
     def run(self, requests: List[Request], clock=time.perf_counter) -> Dict:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
