@@ -185,6 +185,27 @@ FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, c
                                 int32_t *out_counts, void *workspace, size_t workspace_bytes,
                                 void *stream);
 
+/* For callers that cannot allocate device memory at all (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * computation and arguments as flash_query_batch, without the workspace.  Its
+ * scratch (the query keys, stage lists and counters) lives in a fixed area
+ * owned by the library, flash_noalloc_scratch_bytes() bytes (32 MiB) on each
+ * device it runs on, held until the process ends; nothing is allocated by
+ * this call.  A batch whose flash_workspace_bytes(FLASH_OP_QUERY) exceeds
+ * that size is refused with FLASH_ENOSPC before anything is enqueued (about
+ * 246,000 queries at L = 32, 127,000 at L = 64).  Every call on one device
+ * shares that device's area: calls that overlap on one device (other
+ * streams, other threads) race and give wrong results, so order them on one
+ * stream.  The area's first use on a device looks its address up once. */
+FLASH_API int flash_query_batch_noalloc(const flash_params *p, const uint32_t *counts,
+                                        const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+                                        int64_t nnz, const int64_t *q_row_ptr,
+                                        const int32_t *q_col_idx, const int32_t *self_ids, int32_t k,
+                                        int32_t *out_ids, int32_t *out_counts, void *stream);
+
+/* Host only.  Size of the fixed scratch area of flash_query_batch_noalloc. */
+FLASH_API size_t flash_noalloc_scratch_bytes(void);
+
 /* Alg. 3 for a batch whose queries want different k (batched uneven
  * queries).  As flash_query_keys, except that query q returns its first
  * k_per_query[q] ids (device int32[n_queries]; values are clamped to

@@ -392,6 +392,82 @@ FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, c
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
+}  // extern "C"
+
+namespace {
+
+// Library-owned scratch of flash_query_batch_noalloc: query keys, the stage
+// lists and their counters, carved exactly as that call's workspace.  Every
+// device holds its own copy; host code reaches it only through the address
+// hipGetSymbolAddress reports for the current device.
+constexpr size_t kNoAllocScratchBytes = (size_t)32 << 20;
+__device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` on the current device (looked up once per
+// device), or null with *err set.
+void* scratch_address(hipError_t* err) {
+  static std::mutex mu;
+  static void* addr[64] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) {
+    *err = e;
+    return nullptr;
+  }
+  if (dev < 0 || dev >= 64) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+      *err = e != hipSuccess ? e : hipErrorInvalidSymbol;
+      return nullptr;
+    }
+    addr[dev] = p;
+  }
+  return addr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+FLASH_API size_t flash_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
+
+FLASH_API int flash_query_batch_noalloc(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+                                        int64_t n_indexed, int64_t n_queries, int64_t nnz,
+                                        const int64_t* q_row_ptr, const int32_t* q_col_idx,
+                                        const int32_t* self_ids, int32_t k, int32_t* out_ids,
+                                        int32_t* out_counts, void* stream) {
+  Cfg c;
+  int r = make_cfg(p, &c);
+  if (r) return r;
+  if ((r = check_query(c, n_indexed, n_queries, k))) return r;
+  if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
+  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts))
+    return fail(FLASH_EINVAL, "NULL array");
+  const size_t kb = keys_bytes(c, n_queries);
+  const size_t need = kb + query_ws_bytes(c, n_queries);
+  if (need > kNoAllocScratchBytes)
+    return fail(FLASH_ENOSPC, "batch needs " + std::to_string(need) + " bytes of scratch; the library's fixed area holds " +
+                                  std::to_string(kNoAllocScratchBytes) + " (use flash_query_batch with a workspace)");
+  if (n_queries == 0) return FLASH_OK;
+  hipError_t e = hipSuccess;
+  char* ws = (char*)scratch_address(&e);
+  if (!ws) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+  hipStream_t s = (hipStream_t)stream;
+  uint32_t* qkeys = (uint32_t*)ws;
+  const QueryWs w = query_ws_carve(c, n_queries, ws + kb);
+  e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
+  if (e != hipSuccess) return hip_fail(e, "doph_hash");
+  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k, nullptr, out_ids,
+                   out_counts, w, s);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
+}
+
 FLASH_API int flash_query_keys_mixed(const flash_params* p, const uint32_t* counts, const int32_t* ids,
                                      int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                                      const int32_t* self_ids, const int32_t* k_per_query, int32_t k_max,

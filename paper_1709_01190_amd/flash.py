@@ -84,6 +84,8 @@ def lib():
                              ctypes.c_size_t, _VP],
         "flash_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP,
                               _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_query_batch_noalloc": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32,
+                                      _VP, _VP, _VP],
         "flash_query_keys_mixed": [P, _VP, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP,
                                    _VP, ctypes.c_size_t, _VP],
         "flash_query_batch_mixed": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.c_int32,
@@ -105,6 +107,8 @@ def lib():
         fn = getattr(L, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    L.flash_noalloc_scratch_bytes.argtypes = []
+    L.flash_noalloc_scratch_bytes.restype = ctypes.c_size_t
     for name in ("flash_strerror",):
         getattr(L, name).argtypes = [ctypes.c_int]
         getattr(L, name).restype = ctypes.c_char_p
@@ -249,6 +253,21 @@ def flash_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_id
                                    q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx), _p(self_ids),
                                    k, _p(out_ids), _p(out_counts), _p(workspace),
                                    workspace.numel() * workspace.element_size(), _s(stream)))
+
+
+def flash_query_batch_noalloc(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
+                              self_ids=None, stream=None):
+    q = q_row_ptr.numel() - 1
+    _need(out_ids, q * k, (torch.int32,), "out_ids")
+    _need(out_counts, q * k, (torch.int32,), "out_counts")
+    _need(self_ids, q, (torch.int32,), "self_ids")
+    _check(lib().flash_query_batch_noalloc(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+                                           q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
+                                           _p(self_ids), k, _p(out_ids), _p(out_counts), _s(stream)))
+
+
+def flash_noalloc_scratch_bytes() -> int:
+    return int(lib().flash_noalloc_scratch_bytes())
 
 
 def flash_query_keys_mixed(p, counts, ids, n_indexed, qkeys, k_per_query, k_max, out_ids,

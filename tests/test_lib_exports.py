@@ -164,3 +164,22 @@ def test_shared_pool_size_matches_the_oracle(fl, orc):
         ce, ie = fl.flash_index_elems(fl.flash_params.make(K, L, b, R, share_permille=permille))
         P = orc.pool_size(orc.params(K, L, b, R, share_permille=permille))
         assert ce == P and ie == P * R, (K, L, b, permille)
+
+
+def test_noalloc_query_checks_its_fixed_scratch_on_the_host(fl):
+    # the batch is refused before anything touches the GPU when its keys and
+    # stage lists do not fit the library's 32 MiB area
+    L = fl.lib()
+    vp = ctypes.c_void_p(16)
+    assert fl.flash_noalloc_scratch_bytes() == 32 << 20
+    p = fl.flash_params.make(4, 64, 4, 128)
+    need = fl.flash_workspace_bytes(fl.OP_QUERY, p, n_queries=200_000, k=8)
+    assert need > 32 << 20
+    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 200_000, 100, vp, vp, None, 8, vp, vp, None)
+    assert r == fl.FLASH_ENOSPC
+    assert b"scratch" in L.flash_last_error()
+    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 10, 100, vp, vp, None, 0, vp, vp, None)
+    assert r == fl.FLASH_EINVAL
+    # nothing to answer: nothing enqueued
+    assert L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 0, 0, vp, None, None, 8, vp, vp,
+                                       None) == fl.FLASH_OK
