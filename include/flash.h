@@ -279,7 +279,16 @@ typedef struct flash_tuning {
                                     (n_indexed >= R * M, or R * P / L when shared), leave out
                                     the stages whose table holds fewer than L * R candidates;
                                     0 = always run the stages above; default 1 */
-    int32_t reserved[2];
+    int32_t query_filter;        /* 1 = first run every query through the filter stage: one wave
+                                    keeps its <= 2048 candidates in registers, a 32K-bit LDS
+                                    filter finds the ids that may repeat, only those are counted
+                                    exactly, and the smallest ids of count 1 are picked by a radix
+                                    select; queries it cannot finish (more candidates, more than
+                                    128 suspected repeats, or k ids of count >= 2) go on to the
+                                    counting-table stages.  It is left out when full buckets give
+                                    every query more than 2048 candidates.  0 = counting-table
+                                    stages only; default 1 */
+    int32_t reserved;
 } flash_tuning;
 
 /* Current tuning (host struct). */

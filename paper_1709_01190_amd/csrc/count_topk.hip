@@ -91,6 +91,15 @@ __device__ __forceinline__ void tab_reg_add(uint32_t (&r)[LCH], uint32_t t, uint
   }
 }
 
+// The lane index, read so that the compiler cannot hoist what is derived from
+// it out of the query loop (the sorts' per-stage lane masks would otherwise
+// all stay live in scalar registers and spill).
+__device__ __forceinline__ uint32_t opaque_lane() {
+  uint32_t l;
+  asm volatile("v_and_b32 %0, 63, %1" : "=v"(l) : "v"((uint32_t)threadIdx.x));
+  return l;
+}
+
 // Sort m <= 64 * KPL keys held in scratch (ascending) across the wave, KPL
 // keys per lane (element i = lane * KPL + r), and write the first k as
 // (id, count); positions past m get (-1, 0).
@@ -98,7 +107,7 @@ template <int KPL>
 __device__ __forceinline__ void sort_write(const uint32_t* scratch, uint32_t m, uint32_t k, uint32_t L,
                                            uint32_t idshift, uint32_t idmask, int32_t* out_ids,
                                            int32_t* out_counts) {
-  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t lane = opaque_lane();
   uint32_t x[KPL];
 #pragma unroll
   for (int r = 0; r < KPL; ++r) {
@@ -831,6 +840,465 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
   }
 }
 
+// ---------------------------------------------------------------------------
+// First stage for queries of at most 2048 candidates whose ids are nearly all
+// distinct (the usual case: a query meets a few ids in several tables and
+// many once).  One wave per query keeps all its candidates in registers (up
+// to 32 per lane) and needs no full counting table:
+//   a. every candidate sets its bit in a 32K-bit LDS filter; one whose bit
+//      was already set is a suspect (a repeated id, or another id with the
+//      same bit);
+//   b. the suspects go into a small exact table, and a second pass counts
+//      every candidate that is in it.  A candidate not in it occurs exactly
+//      once: had its id occurred before, that earlier occurrence would have
+//      set the bit and made this one a suspect;
+//   c. the ids of count >= 2 (all in the table) come first; the rest of the
+//      k places go to the smallest ids of count 1, found by a radix select
+//      over id bins (the bin holding the cut is ranked directly, or refined
+//      when crowded).
+// Queries with more candidates or suspects than the stage holds, or with at
+// least k ids of count >= 2 (the threshold count is then above 1), are
+// handed on to the counting-table stages.
+constexpr int kFastU = 8;                  // tasks of 4 candidates per lane
+constexpr uint32_t kFastCap = 64 * 4 * kFastU;
+constexpr uint32_t kBmWords = 1024;        // filter bits: 32 * 1024
+constexpr uint32_t kTs = 256;              // suspect table slots
+constexpr uint32_t kSusp = 128;            // suspects a query may have
+constexpr int kNB = 512;                   // radix bins
+constexpr uint32_t kCut = 64;              // a cut bin of at most this many ids is ranked directly
+
+__host__ __device__ inline uint32_t fast_union_words(uint32_t kmax) {
+  const uint32_t select = (uint32_t)kNB + kCut + ((kmax + 3u) & ~3u);
+  return select > 64u * kFastU ? select : 64u * kFastU;
+}
+// LDS words: filter, suspect keys and counts, suspect list, table info,
+// window marks / radix bins / cut bin / survivor keys
+__host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
+  return kBmWords + 2 * kTs + kSusp + 4u * (uint32_t)L + fast_union_words(kmax);
+}
+
+__device__ __forceinline__ uint32_t filter_bit(uint32_t id) { return (id * 0x9E3779B1u) >> 17; }
+__device__ __forceinline__ uint32_t ts_slot(uint32_t id) { return (id * 0x85EBCA77u) >> 24; }
+
+// Bins [0, 512): lane l holds bins 8l .. 8l+7.  Returns the bin b* where the
+// running count first reaches `need` (1 <= need <= total), with *before =
+// the count of the bins below it and *inb = its own.
+__device__ __forceinline__ uint32_t find_cut_bin(const uint32_t* bins, uint32_t need, uint32_t* before,
+                                                 uint32_t* inb) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint4 b0 = *reinterpret_cast<const uint4*>(bins + 8 * lane);
+  const uint4 b1 = *reinterpret_cast<const uint4*>(bins + 8 * lane + 4);
+  const uint32_t v[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+  uint32_t sum = 0;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) sum += v[i];
+  const uint32_t incl = wave_incl_scan(sum);
+  const uint32_t excl = incl - sum;
+  const uint64_t hit = __ballot(excl < need && need <= incl);
+  const uint32_t f = hit ? (uint32_t)__ffsll((unsigned long long)hit) - 1 : 63u;
+  uint32_t run = excl, bin = 0, bef = 0, own = 0;
+  bool done = false;
+#pragma unroll
+  for (int i = 0; i < 8; ++i) {
+    if (!done && run + v[i] >= need) {
+      bin = 8 * lane + (uint32_t)i;
+      bef = run;
+      own = v[i];
+      done = true;
+    }
+    run += v[i];
+  }
+  *before = rl(bef, f);
+  *inb = rl(own, f);
+  return rl(bin, f);
+}
+
+__device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64u - (uint32_t)__clzll((long long)x) : 0u; }
+
+template <int LCH, bool ALIGNED>
+__global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
+  constexpr int U = kFastU;
+  constexpr int W = kWave * U;
+  constexpr int NJ = 4 * U;
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t kmax = (uint32_t)a.k;
+  uint32_t* bm = (uint32_t*)smem;                       // [kBmWords] filter
+  uint32_t* tsk = bm + kBmWords;                         // [kTs] suspect ids
+  uint32_t* tsc = tsk + kTs;                             // [kTs] their counts
+  uint32_t* susp = tsc + kTs;                            // [kSusp] suspect list
+  uint4* tinfo = reinterpret_cast<uint4*>(susp + kSusp); // [L]
+  uint32_t* un = reinterpret_cast<uint32_t*>(tinfo + a.L);
+  uint32_t* marks = un;                                  // [W] window marks
+  uint32_t* bins = un;                                   // [kNB] radix bins
+  uint32_t* cutb = un + kNB;                             // [kCut] ids of the cut bin
+  uint32_t* surv = un + kNB + kCut;                      // [kmax] survivor keys
+
+  const uint32_t lane = threadIdx.x;
+  const uint32_t L = (uint32_t)a.L;
+  const uint32_t R = (uint32_t)a.R;
+  const uint32_t cb = (uint32_t)a.cbits;
+  const uint32_t idshift = 32u - cb;
+  const uint32_t idmask = (idshift >= 32) ? 0xFFFFFFFFu : ((1u << idshift) - 1u);
+  uint4* bm4 = reinterpret_cast<uint4*>(bm);
+  for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
+  for (uint32_t i = lane; i < kTs; i += kWave) {
+    tsk[i] = kEmpty;
+    tsc[i] = 0;
+  }
+  for (uint32_t i = lane; i < (uint32_t)W; i += kWave) marks[i] = kEmpty;
+  __syncthreads();
+
+  uint32_t ovf_buf = 0, ovf_n = 0;
+  const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
+  // the next query's keys and bucket counts are loaded while the current one
+  // is processed: key[c] / cnt[c] of lane t = table c * 64 + t
+  uint32_t pkey[LCH], pcnt[LCH];
+  auto load_keys = [&](uint64_t wq) {
+    const uint64_t qq = wq < nq ? (a.qlist ? (uint64_t)a.qlist[wq] : wq) : 0;
+#pragma unroll
+    for (int c = 0; c < LCH; ++c) {
+      const uint32_t t = (uint32_t)c * 64 + lane;
+      pkey[c] = (wq < nq && t < L) ? a.qkeys[qq * (uint64_t)L + t] : kEmpty;
+    }
+  };
+  auto load_counts = [&]() {
+#pragma unroll
+    for (int c = 0; c < LCH; ++c) {
+      const uint32_t t = (uint32_t)c * 64 + lane;
+      pcnt[c] = pkey[c] < a.M ? a.counts[reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, pkey[c])] : 0u;
+    }
+  };
+  load_keys(blockIdx.x);
+  load_counts();
+  for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
+    const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
+    const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
+    const uint32_t k = query_k(a, q, kmax);
+
+    // 1. occupancy, as in the counting-table stages
+    uint32_t tstart[LCH], tcnt[LCH];
+    uint32_t carry = 0;
+#pragma unroll
+    for (int c = 0; c < LCH; ++c) {
+      const uint32_t t = (uint32_t)c * 64 + lane;
+      uint32_t nt = 0;
+      uint64_t base = 0;
+      if (pkey[c] < a.M) {
+        const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, pkey[c]);
+        nt = pcnt[c] < R ? pcnt[c] : R;
+        base = bucket * R;
+      }
+      const uint32_t ct = (nt + 3) >> 2;
+      const uint32_t packed = (nt << 16) | ct;
+      const uint32_t inc = wave_incl_scan(packed);
+      const uint32_t pre = carry + inc - packed;
+      tstart[c] = pre & 0xFFFFu;
+      tcnt[c] = ct;
+      if (t < L)
+        tinfo[t] = make_uint4((uint32_t)(base - 4ull * tstart[c]), (uint32_t)((base - 4ull * tstart[c]) >> 32),
+                              4u * tstart[c] + nt, 0u);
+      carry += rl(inc, 63);
+    }
+    const uint32_t total = carry >> 16, n_tasks = carry & 0xFFFFu;
+    load_keys(w + gridDim.x);
+    bool hand_on = total > kFastCap || n_tasks > (uint32_t)W;
+    const bool touched = !hand_on;
+    uint32_t idv[NJ];
+    uint32_t nsus = 0;
+    if (!hand_on) {
+      // 2. gather every candidate (the tasks fit one window); an absent or
+      // excluded candidate becomes kEmpty
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) {
+        const uint32_t t = (uint32_t)c * 64 + lane;
+        if (tcnt[c] > 0 && tstart[c] > 0) marks[tstart[c]] = t;
+      }
+      uint32_t tf = 0;
+#pragma unroll
+      for (int c = 0; c < LCH; ++c) {
+        const uint64_t bal = __ballot(tcnt[c] > 0 && tstart[c] == 0);
+        if (bal) tf = (uint32_t)c * 64 + (uint32_t)__ffsll((unsigned long long)bal) - 1;
+      }
+      if (lane == 0) marks[0] = tf;
+      wave_lds_sync();
+      uint32_t tcarry = 0;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        idv[4 * u + 0] = idv[4 * u + 1] = idv[4 * u + 2] = idv[4 * u + 3] = kEmpty;
+        if ((uint32_t)u * kWave < n_tasks) {
+          const uint32_t mk = marks[u * kWave + lane];
+          marks[u * kWave + lane] = kEmpty;
+          uint32_t tt = wave_incl_max(mk == kEmpty ? 0u : mk + 1);
+          tt = tt > tcarry ? tt : tcarry;
+          tcarry = rl(tt, 63);
+          const uint32_t task = (uint32_t)u * kWave + lane;
+          const uint32_t tc = task < n_tasks ? task : n_tasks - 1;
+          const uint4 ti = tinfo[tt - 1];
+          const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
+          const uint32_t room = ti.z - 4u * tc;
+          const uint32_t vm = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
+          uint4 v4;
+          if (ALIGNED) {
+            v4 = *reinterpret_cast<const uint4*>(a.ids + addr);
+          } else {
+            const uint32_t last = room - 1;
+            v4.x = (uint32_t)a.ids[addr];
+            v4.y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
+            v4.z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
+            v4.w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
+          }
+          const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            idv[4 * u + i] = (((vm >> i) & 1u) && (int64_t)vv[i] != self) ? vv[i] : kEmpty;
+        }
+      }
+      load_counts();
+      // 3a. filter: a candidate whose bit is already set is a suspect
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if ((uint32_t)u * kWave < n_tasks) {
+          uint32_t seen[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t x = idv[4 * u + i];
+            const uint32_t b = filter_bit(x);
+            const uint32_t bit = 1u << (b & 31u);
+            seen[i] = x != kEmpty ? (atomicOr(&bm[b >> 5], bit) & bit) : 0u;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint64_t m = __ballot(seen[i] != 0);
+            if (m) {
+              const uint32_t p = nsus + mbcnt(m);
+              if (seen[i] && p < kSusp) susp[p] = idv[4 * u + i];
+              nsus += (uint32_t)__popcll(m);
+            }
+          }
+        }
+      }
+      hand_on = nsus > kSusp;
+    }
+    if (!touched) load_counts();
+    uint32_t nmulti = 0, nsing = 0;
+    if (!hand_on) {
+      wave_lds_sync();
+      // 3b. the suspects into the exact table (ids only; linear probing, at
+      // most half full)
+      for (uint32_t i = lane; i < nsus; i += kWave) {
+        const uint32_t x = susp[i];
+        uint32_t sl = ts_slot(x);
+        for (;;) {
+          const uint32_t o = atomicCAS(&tsk[sl], kEmpty, x);
+          if (o == kEmpty || o == x) break;
+          sl = (sl + 1) & (kTs - 1);
+        }
+      }
+      wave_lds_sync();
+      // 3c. count every candidate that is a suspect; the others occur once
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if ((uint32_t)u * kWave < n_tasks) {
+          uint32_t sl[4], o[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            sl[i] = ts_slot(idv[4 * u + i]);
+            o[i] = idv[4 * u + i] != kEmpty ? tsk[sl[i]] : kEmpty;
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t x = idv[4 * u + i];
+            if (x != kEmpty && o[i] != kEmpty) {
+              uint32_t s2 = sl[i], o2 = o[i];
+              while (o2 != x && o2 != kEmpty) {
+                s2 = (s2 + 1) & (kTs - 1);
+                o2 = tsk[s2];
+              }
+              if (o2 == x) {
+                atomicAdd(&tsc[s2], 1u);
+                idv[4 * u + i] = kEmpty;
+              }
+            }
+            nsing += (uint32_t)__popcll(__ballot(idv[4 * u + i] != kEmpty));
+          }
+        }
+      }
+      wave_lds_sync();
+      // the table's ids of count >= 2, and of count 1 (they occur once:
+      // their bit was set by another id)
+      uint32_t nm = 0, n1 = 0;
+      for (uint32_t i = lane; i < kTs; i += kWave) {
+        const uint32_t c = tsk[i] != kEmpty ? tsc[i] : 0u;
+        nm += c >= 2;
+        n1 += c == 1;
+      }
+      nmulti = wave_sum(nm);
+      nsing += wave_sum(n1);
+      hand_on = nmulti >= k;
+    }
+    if (hand_on) {
+      if (lane == ovf_n) ovf_buf = (uint32_t)q;
+      if (++ovf_n == (uint32_t)kWave) ovf_n = flush_overflow(a, ovf_buf, ovf_n);
+    } else {
+      // 4. ids of count >= 2 all survive; then the `need` smallest ids of
+      // count 1: ids below x_lo, and the smallest `cut` of [x_lo, x_hi)
+      const uint32_t D = nsing + nmulti;
+      const uint32_t need = (D <= k ? D : k) - nmulti;
+      // ranges in 32 bits: ids are below 2^31, so 0xFFFFFFFF stands for 2^32
+      uint32_t x_lo = kEmpty, x_hi = kEmpty;
+      uint32_t cut = 0;
+      if (need < nsing) {
+        const uint64_t span = (uint64_t)(a.n_indexed > 0 ? a.n_indexed : 1);
+        uint64_t est = 2ull * need * span / nsing + 64;
+        if (est > span) est = span;
+        uint32_t s = bitlen64(est - 1) > 9 ? bitlen64(est - 1) - 9 : 0;
+        // level 0 covers [0, 511 << s) and bin 511 takes the ids above; a
+        // deeper level covers the cut bin [lo, lo + wid) of the level before
+        uint32_t lo = 0, wid = (uint32_t)(kNB - 1) << s;
+        uint32_t needl = need;
+        for (int level = 0;; ++level) {
+          for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave)
+            reinterpret_cast<uint4*>(bins)[i] = make_uint4(0, 0, 0, 0);
+          wave_lds_sync();
+          auto bin_of = [&](uint32_t x) {
+            const uint32_t d = x - lo;   // wraps above wid for x < lo (lo + wid <= 2^32)
+            if (x != kEmpty) {
+              if (d < wid) atomicAdd(&bins[d >> s], 1u);
+              else if (level == 0) atomicAdd(&bins[kNB - 1], 1u);
+            }
+          };
+#pragma unroll
+          for (int u = 0; u < U; ++u)
+            if ((uint32_t)u * kWave < n_tasks) {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) bin_of(idv[4 * u + i]);
+            }
+          for (uint32_t i = lane; i < kTs; i += kWave) bin_of(tsc[i] == 1 ? tsk[i] : kEmpty);
+          wave_lds_sync();
+          uint32_t before, inb;
+          const uint32_t bs = find_cut_bin(bins, needl, &before, &inb);
+          uint32_t nlo, nwid;
+          if (level == 0 && bs == (uint32_t)kNB - 1) {
+            nlo = wid;
+            nwid = kEmpty - wid;   // [wid, 2^32)
+          } else {
+            nlo = lo + (bs << s);
+            const uint32_t rest = wid - (bs << s);
+            nwid = (1u << s) < rest ? (1u << s) : rest;
+          }
+          needl -= before;
+          // each level narrows the range 2^9-fold: ids below 2^32 need at
+          // most four levels; the bound only guards the loop
+          if (inb <= kCut || level >= 5) {
+            x_lo = nlo;
+            x_hi = nlo + nwid;
+            if (x_hi < nlo) x_hi = kEmpty;
+            cut = needl;
+            break;
+          }
+          lo = nlo;
+          wid = nwid;
+          s = bitlen64(wid - 1) > 9 ? bitlen64(wid - 1) - 9 : 0;
+          wave_lds_sync();
+        }
+      }
+      // survivor keys: count >= 2, then count-1 ids below x_lo, then the
+      // ranked cut bin
+      uint32_t m = 0, ncut = 0;
+      for (uint32_t i0 = 0; i0 < kTs; i0 += kWave) {
+        const uint32_t x = tsk[i0 + lane];
+        const uint32_t c = x != kEmpty ? tsc[i0 + lane] : 0u;
+        const bool mult = c >= 2, one = c == 1;
+        const bool all = one && x < x_lo;
+        const bool part = one && x >= x_lo && x < x_hi;
+        const uint64_t mm = __ballot(mult || all);
+        if (mult || all) surv[m + mbcnt(mm)] = ((L - (mult ? c : 1u)) << idshift) | x;
+        m += (uint32_t)__popcll(mm);
+        const uint64_t mp = __ballot(part);
+        if (part && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = x;
+        ncut += (uint32_t)__popcll(mp);
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        if ((uint32_t)u * kWave < n_tasks) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t x = idv[4 * u + i];
+            const bool all = x < x_lo;   // kEmpty never passes
+            const bool part = x != kEmpty && x >= x_lo && x < x_hi;
+            const uint64_t mm = __ballot(all);
+            if (all) surv[m + mbcnt(mm)] = ((L - 1u) << idshift) | x;
+            m += (uint32_t)__popcll(mm);
+            const uint64_t mp = __ballot(part);
+            if (mp) {
+              if (part && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = x;
+              ncut += (uint32_t)__popcll(mp);
+            }
+          }
+        }
+      }
+      wave_lds_sync();
+      if (ncut > kCut) ncut = kCut;   // not reached: the cut bin holds at most kCut ids
+      if (ncut) {
+        const uint32_t mine = lane < ncut ? cutb[lane] : 0u;
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < ncut; ++j) rank += cutb[j] < mine;
+        const bool sel = lane < ncut && rank < cut;
+        const uint64_t mm = __ballot(sel);
+        if (sel) surv[m + mbcnt(mm)] = ((L - 1u) << idshift) | mine;
+        m += (uint32_t)__popcll(mm);
+        wave_lds_sync();
+      }
+      const uint64_t orow = q * (uint64_t)kmax;
+      for (uint32_t j = k + lane; j < kmax; j += kWave) {
+        a.out_ids[orow + j] = -1;
+        a.out_counts[orow + j] = 0;
+      }
+      if (m <= 64) {
+        sort_write<1>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else if (m <= 128) {
+        sort_write<2>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else if (m <= 256) {
+        sort_write<4>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      } else {
+        rank_write(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      }
+    }
+    // 5. leave the filter, the suspect table and the window marks
+    // (overwritten by the selection buffers) empty for the next query
+    wave_lds_sync();
+    if (touched) {
+      for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
+      if (nsus) {
+        reinterpret_cast<uint4*>(tsk)[lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+        reinterpret_cast<uint4*>(tsc)[lane] = make_uint4(0, 0, 0, 0);
+      }
+      for (uint32_t i = lane; i < (uint32_t)W; i += kWave) marks[i] = kEmpty;
+    }
+    wave_lds_sync();
+  }
+  if (ovf_n) flush_overflow(a, ovf_buf, ovf_n);
+}
+
+template <int LCH, bool ALIGNED>
+hipError_t launch_fast(const QueryArgs& a, int grid, hipStream_t st) {
+  const size_t lds = 4 * (size_t)fast_lds_words(a.L, (uint32_t)a.k);
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_fast_kernel<LCH, ALIGNED>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((count_topk_fast_kernel<LCH, ALIGNED>), dim3(grid), dim3(64), lds, st, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_fast_any(const QueryArgs& a, bool aligned, int grid, hipStream_t st) {
+  switch ((a.L + 63) / 64) {
+    case 1: return aligned ? launch_fast<1, true>(a, grid, st) : launch_fast<1, false>(a, grid, st);
+    case 2: return aligned ? launch_fast<2, true>(a, grid, st) : launch_fast<2, false>(a, grid, st);
+    case 3: return aligned ? launch_fast<3, true>(a, grid, st) : launch_fast<3, false>(a, grid, st);
+    case 4: return aligned ? launch_fast<4, true>(a, grid, st) : launch_fast<4, false>(a, grid, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 template <int CAP, int LCH, bool ALIGNED>
 hipError_t launch_kernel(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = smem_bytes(CAP, a.L, a.sb);
@@ -991,12 +1459,24 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
 
   const int cus = device_info().cus;
   const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 256;
+  // the filter stage goes first unless every query is sure to exceed it
+  // (full buckets with more than its 2048 candidates)
+  const bool filter = tu.query_filter != 0 && !(skip_small && full > kFastCap);
+  const int first = filter ? 1 : 0;   // stage index of the first counting-table stage
   hipError_t e;
-  if (n_stage > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
-  for (int s = 0; s < n_stage; ++s) {
+  if ((n_stage + first) > 1 && (e = launch_fill_u32(w.ovf_len, 4, 0u, st)) != hipSuccess) return e;
+  if (filter) {
     QueryArgs b = a;
-    const bool final_stage = s == n_stage - 1;
-    b.max_total = final_stage ? full : (uint32_t)caps[s] * 3 / 4;
+    b.ovf_list = w.ovf_list[0];
+    b.ovf_len = w.ovf_len;
+    const int64_t want = (int64_t)cus * per_cu;
+    if ((e = launch_fast_any(b, a.r_aligned != 0, (int)(n_queries < want ? n_queries : want), st)) != hipSuccess) return e;
+  }
+  for (int s = first; s < n_stage + first; ++s) {
+    QueryArgs b = a;
+    const int cs = s - first;   // index into caps
+    const bool final_stage = s == n_stage + first - 1;
+    b.max_total = final_stage ? full : (uint32_t)caps[cs] * 3 / 4;
     const uint32_t need_sb = (uint32_t)k + slack_for((uint32_t)k);
     b.sb = need_sb < b.max_total ? need_sb : (b.max_total > (uint32_t)k ? b.max_total : (uint32_t)k);
     b.sb = (b.sb + 3) & ~3u;  // keeps tinfo 16-byte aligned
@@ -1007,22 +1487,24 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     if (!final_stage) {
       b.ovf_list = w.ovf_list[s & 1];
       b.ovf_len = w.ovf_len + (s & 1);
+      // the list this stage fills was last read by the stage before
+      if (s >= 2 && (e = launch_fill_u32(w.ovf_len + (s & 1), 1, 0u, st)) != hipSuccess) return e;
     }
     if (final_stage && nw > 1) {
       // as many workgroups as fit on the CUs at once (LDS and 32 waves per CU)
-      const size_t lds = block_smem_bytes(caps[s], c.L, b.sb, nw);
+      const size_t lds = block_smem_bytes(caps[cs], c.L, b.sb, nw);
       int per = (int)((160 * 1024) / lds);
       if (per > 32 / nw) per = 32 / nw;
       if (per < 1) per = 1;
       const int64_t want = (int64_t)cus * per;
       const int grid = (int)(n_queries < want ? n_queries : want);
-      if ((e = launch_block_any(nw, caps[s], b, grid, st)) != hipSuccess) return e;
+      if ((e = launch_block_any(nw, caps[cs], b, grid, st)) != hipSuccess) return e;
       continue;
     }
     int64_t want = (int64_t)cus * per_cu;
     if (s > 0) want = (int64_t)cus * 8;
     const int grid = (int)(n_queries < want ? n_queries : want);
-    if ((e = launch_any(caps[s], b, grid, st)) != hipSuccess) return e;
+    if ((e = launch_any(caps[cs], b, grid, st)) != hipSuccess) return e;
   }
   return hipSuccess;
 }

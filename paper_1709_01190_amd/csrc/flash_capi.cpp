@@ -156,7 +156,7 @@ int tuning_from_c(const flash_tuning* t, Tuning* out) {
     *out = Tuning();
     return FLASH_OK;
   }
-  if (t->reserved[0] || t->reserved[1])
+  if (t->reserved)
     return fail(FLASH_EINVAL, "tuning.reserved must be 0");
   for (int v : {t->query_cap1, t->query_cap2})
     if (v != 0 && (v < 1024 || v > 16384)) return fail(FLASH_EINVAL, "query caps must be 0 or in [1024, 16384]");
@@ -167,12 +167,14 @@ int tuning_from_c(const flash_tuning* t, Tuning* out) {
   if (t->hash_tile_rows < 0 || t->hash_tile_rows > 65536)
     return fail(FLASH_EINVAL, "hash_tile_rows must be in [0, 65536]");
   if (t->query_skip_full != 0 && t->query_skip_full != 1) return fail(FLASH_EINVAL, "query_skip_full must be 0 or 1");
+  if (t->query_filter != 0 && t->query_filter != 1) return fail(FLASH_EINVAL, "query_filter must be 0 or 1");
   out->query_cap1 = t->query_cap1;
   out->query_cap2 = t->query_cap2;
   out->query_blocks_per_cu = t->query_blocks_per_cu;
   out->query_big_waves = t->query_big_waves;
   out->hash_tile_rows = t->hash_tile_rows;
   out->query_skip_full = t->query_skip_full;
+  out->query_filter = t->query_filter;
   return FLASH_OK;
 }
 
@@ -184,6 +186,7 @@ flash_tuning tuning_to_c(const Tuning& t) {
   o.query_big_waves = t.query_big_waves;
   o.hash_tile_rows = t.hash_tile_rows;
   o.query_skip_full = t.query_skip_full;
+  o.query_filter = t.query_filter;
   return o;
 }
 
@@ -630,10 +633,11 @@ FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* 
   const int per_cu[] = {64, 128, 256, 512};
   const int tiles[] = {0, 4, 16, 64};
   // the full-bucket stage skip first: it decides whether the stage layouts differ
-  for (int field = 0; field < 5 && !rc; ++field) {
-    const int n = field == 0 ? 2 : (field == 2 ? 6 : 4);
+  for (int field = 0; field < 6 && !rc; ++field) {
+    const int n = (field == 0 || field == 5) ? 2 : (field == 2 ? 6 : 4);
     for (int i = 0; i < n && !rc; ++i) {
       Tuning t = cur;
+      if (field == 5) t.query_filter = 1 - i;
       if (field == 0) t.query_skip_full = 1 - i;
       if (field == 1) t.query_big_waves = waves[i];
       if (field == 2) {

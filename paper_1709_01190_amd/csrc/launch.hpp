@@ -39,6 +39,7 @@ struct Tuning {
   int query_big_waves = 8;        // waves per workgroup in a last stage of >= 8192 entries (1: one wave)
   int hash_tile_rows = 0;         // 0: static row stride; else rows per tile taken from a work counter
   int query_skip_full = 1;        // leave out stages too small for L * R candidates when buckets are full
+  int query_filter = 1;           // run the filter stage (ids of count 1 told apart without a counting table) first
 };
 Tuning tuning();
 

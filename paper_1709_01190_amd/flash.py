@@ -51,7 +51,7 @@ class flash_tuning(ctypes.Structure):
     _fields_ = [("query_cap1", ctypes.c_int32), ("query_cap2", ctypes.c_int32),
                 ("query_blocks_per_cu", ctypes.c_int32), ("query_big_waves", ctypes.c_int32),
                 ("hash_tile_rows", ctypes.c_int32), ("query_skip_full", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("query_filter", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
     def as_dict(self) -> dict:
         return {f: int(getattr(self, f)) for f, _ in self._fields_ if f != "reserved"}

@@ -280,8 +280,11 @@ def tuned(fl):
 # stage) and the waves per workgroup of a large last stage
 # (query_skip_full=0 keeps the small stages even where the buckets are full;
 # the defaults, with the skip, come first)
-STAGE_SHAPES = [dict()] + [dict(query_cap1=c1, query_cap2=c2, query_big_waves=w, query_skip_full=0)
-                           for (c1, c2) in ((1024, 4096), (2048, 0), (0, 0), (16384, 0)) for w in (1, 4, 8, 16)]
+# (query_filter=0 sends every query to the counting-table stages; with the
+# filter stage on they see only the queries it hands on)
+STAGE_SHAPES = [dict(), dict(query_filter=0)] + [
+    dict(query_cap1=c1, query_cap2=c2, query_big_waves=w, query_skip_full=0, query_filter=f)
+    for (c1, c2) in ((1024, 4096), (2048, 0), (0, 0), (16384, 0)) for w in (1, 4, 8, 16) for f in (0, 1)]
 
 
 def test_query_overflow_table(fl, orc, tuned):
@@ -342,13 +345,56 @@ def test_query_many_tables(fl, orc):
     assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
+@pytest.mark.parametrize("case", ["repeats", "crowded", "high_ids", "k_edges"])
+def test_filter_stage_edges(fl, orc, tuned, case):
+    # the filter stage's limits, with the stage on and off, against the oracle:
+    # repeats: 1000 identical rows, so queries bring ~1000 repeated ids (more
+    #   suspects than the stage holds, or k ids of count >= 2: handed on);
+    # crowded: n_indexed far above every stored id, so the first radix level
+    #   puts all ids in one bin and the select refines it;
+    # high_ids: the queries meet only the last 1000 rows, far above the
+    #   expected cut, so the cut falls in the first level's overflow bin;
+    # k_edges: k = 1 and k = 1024 (all candidates survive).
+    say("filter stage", case)
+    rng = np.random.default_rng(31)
+    K, L, b, R = 1, 32, 3, 64
+    n = 20000
+    nq = 500
+    keys = rng.integers(0, 1 << (K * b), size=(n, L)).astype(np.uint32)
+    n_indexed = n
+    ks = [64]
+    if case == "repeats":
+        keys[500:1500] = keys[0]
+    elif case == "crowded":
+        n_indexed = 1 << 26   # the largest the packed query table takes at L = 32
+    elif case == "high_ids":
+        K, b = 1, 6
+        keys = rng.integers(0, 32, size=(n, L)).astype(np.uint32)
+        keys[n - 1000:] = rng.integers(32, 64, size=(1000, L))
+    else:
+        ks = [1, 1024]
+    op = orc.params(K, L, b, R, seed=12)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(K, L, b, R, seed=12)
+    counts, ids = gpu_insert(fl, p, keys)
+    qk = keys[n - nq:] if case == "high_ids" else keys[:nq]
+    sid = np.arange(n - nq, n, dtype=np.int32) if case == "high_ids" else np.arange(nq, dtype=np.int32)
+    for k in ks:
+        wi, wc = orc.query(op, ocounts, oids, qk, k, self_ids=sid)
+        for filt in (1, 0):
+            tuned(None)
+            tuned(query_filter=filt)
+            oi, oc = gpu_query(fl, p, counts, ids, n_indexed, qk, k, sid)
+            assert np.array_equal(oi, wi) and np.array_equal(oc, wc), (case, k, filt)
+
+
 def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, tuned):
     say("query launch shapes")
     p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
     n = keys.shape[0]
     ref = None
-    for per_cu in (1, 4, 32):
-        tuned(query_blocks_per_cu=per_cu)
+    for per_cu, filt in ((1, 1), (4, 0), (32, 1), (32, 0)):
+        tuned(query_blocks_per_cu=per_cu, query_filter=filt)
         out = gpu_query(fl, p, counts, ids, n, keys, 16, np.arange(n, dtype=np.int32))
         if ref is None:
             ref = out

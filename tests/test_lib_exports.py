@@ -109,18 +109,19 @@ def test_tuning_is_checked_and_restorable(fl):
     fl.flash_set_tuning(None)
     d = fl.flash_get_tuning().as_dict()
     assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 256,
-                 "query_big_waves": 8, "hash_tile_rows": 0, "query_skip_full": 1}
+                 "query_big_waves": 8, "hash_tile_rows": 0, "query_skip_full": 1, "query_filter": 1}
     fl.flash_set_tuning(query_big_waves=16, hash_tile_rows=32, query_cap2=0)
     d2 = fl.flash_get_tuning().as_dict()
     assert d2["query_big_waves"] == 16 and d2["hash_tile_rows"] == 32 and d2["query_cap2"] == 0
     for bad in (dict(query_big_waves=3), dict(query_cap1=512), dict(query_cap2=32768),
-                dict(query_blocks_per_cu=0), dict(hash_tile_rows=-1), dict(query_skip_full=2)):
+                dict(query_blocks_per_cu=0), dict(hash_tile_rows=-1), dict(query_skip_full=2),
+                dict(query_filter=3)):
         with pytest.raises(fl.FlashError) as e:
             fl.flash_set_tuning(**bad)
         assert e.value.code == fl.FLASH_EINVAL
         assert fl.flash_get_tuning().as_dict() == d2       # a rejected tuning changes nothing
     t = fl.flash_get_tuning()
-    t.reserved[1] = 7
+    t.reserved = 7
     with pytest.raises(fl.FlashError):
         fl.flash_set_tuning(t)
     fl.flash_set_tuning(None)
