@@ -867,28 +867,58 @@ constexpr uint32_t kSusp = 128;            // suspects a query may have
 constexpr int kNB = 512;                   // radix bins
 constexpr uint32_t kCut = 64;              // a cut bin of at most this many ids is ranked directly
 
-__host__ __device__ inline uint32_t fast_union_words(uint32_t kmax) {
-  const uint32_t select = (uint32_t)kNB + kCut + ((kmax + 3u) & ~3u);
-  return select > 64u * kFastU ? select : 64u * kFastU;
-}
-// LDS words: filter, suspect keys and counts, suspect list, table info,
-// window marks / radix bins / cut bin / survivor keys
+// window marks: one 16-bit entry (table + 1; 0: none) per task of the window
+constexpr uint32_t kMarkWords = 64 * kFastU / 2;
+static_assert(kMarkWords <= (uint32_t)kNB, "the window marks live in the radix bins");
+// the suspects' own filter (8K bits): a candidate whose bit is clear there is
+// no suspect, so only about one in a hundred probes the suspect table
+constexpr uint32_t kB2Words = 256;
+constexpr uint32_t kStageK = 256;   // rows of up to this k are assembled in LDS
+static_assert(kSusp <= (uint32_t)kNB - kMarkWords, "the suspect list follows the marks in the bins");
+
+// LDS words: filter, suspect ids and counts, table info, radix bins, the cut
+// bin's ids, and (k above kStageK only) survivor keys and tie groups.  Buffers
+// whose lifetimes do not overlap share words:
+//   - the window marks (gather) are the first bins: once read they are zero
+//     again, as the bins must be when counting starts;
+//   - the suspect list (filter, suspect table) is the last 128 bins, cleared
+//     after use;
+//   - the suspects' filter (suspect table, lookup) is the last 256 words of
+//     the first filter, free once every candidate has passed it (cleared
+//     before use);
+//   - with k <= kStageK the output row (ids, then counts) is assembled in the
+//     first filter's first 2k words, and the survivor keys and tie groups
+//     follow at word 512.
+// Everything is zero (filters, bins) or empty (suspect table) between queries.
 __host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
-  return kBmWords + 2 * kTs + kSusp + 4u * (uint32_t)L + fast_union_words(kmax);
+  const uint32_t k4 = (kmax + 3u) & ~3u;
+  return kBmWords + 2 * kTs + 4u * (uint32_t)L + (uint32_t)kNB + kCut + (kmax <= kStageK ? 0u : 2 * k4);
 }
 
 __device__ __forceinline__ uint32_t filter_bit(uint32_t id) { return (id * 0x9E3779B1u) >> 17; }
 __device__ __forceinline__ uint32_t ts_slot(uint32_t id) { return (id * 0x85EBCA77u) >> 24; }
+__device__ __forceinline__ uint32_t b2_bit(uint32_t id) { return (id * 0xC2B2AE35u) >> 19; }
 
 // Bins [0, 512): lane l holds bins 8l .. 8l+7.  Returns the bin b* where the
 // running count first reaches `need` (1 <= need <= total), with *before =
-// the count of the bins below it and *inb = its own.
-__device__ __forceinline__ uint32_t find_cut_bin(const uint32_t* bins, uint32_t need, uint32_t* before,
-                                                 uint32_t* inb) {
+// the count of the bins below it and *inb = its own.  With `prefix`, every
+// bin below b* is replaced by its exclusive prefix (the start of its group).
+// With `all` != 0 the last bin is not counted in LDS: it holds all minus
+// the other bins.
+__device__ __forceinline__ uint32_t find_cut_bin(uint32_t* bins, uint32_t need, uint32_t* before, uint32_t* inb,
+                                                 bool prefix, uint32_t all = 0) {
   const uint32_t lane = threadIdx.x & 63;
-  const uint4 b0 = *reinterpret_cast<const uint4*>(bins + 8 * lane);
-  const uint4 b1 = *reinterpret_cast<const uint4*>(bins + 8 * lane + 4);
-  const uint32_t v[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+  uint4* b4 = reinterpret_cast<uint4*>(bins + 8 * lane);
+  const uint4 b0 = b4[0];
+  const uint4 b1 = b4[1];
+  uint32_t v[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+  if (all) {
+    uint32_t part = 0;
+#pragma unroll
+    for (int i = 0; i < 8; ++i) part += v[i];
+    const uint32_t rest = all - wave_sum(part);
+    if (lane == 63) v[7] += rest;
+  }
   uint32_t sum = 0;
 #pragma unroll
   for (int i = 0; i < 8; ++i) sum += v[i];
@@ -898,8 +928,10 @@ __device__ __forceinline__ uint32_t find_cut_bin(const uint32_t* bins, uint32_t 
   const uint32_t f = hit ? (uint32_t)__ffsll((unsigned long long)hit) - 1 : 63u;
   uint32_t run = excl, bin = 0, bef = 0, own = 0;
   bool done = false;
+  uint32_t pre[8];
 #pragma unroll
   for (int i = 0; i < 8; ++i) {
+    pre[i] = run;
     if (!done && run + v[i] >= need) {
       bin = 8 * lane + (uint32_t)i;
       bef = run;
@@ -907,6 +939,10 @@ __device__ __forceinline__ uint32_t find_cut_bin(const uint32_t* bins, uint32_t 
       done = true;
     }
     run += v[i];
+  }
+  if (prefix) {
+    b4[0] = make_uint4(pre[0], pre[1], pre[2], pre[3]);
+    b4[1] = make_uint4(pre[4], pre[5], pre[6], pre[7]);
   }
   *before = rl(bef, f);
   *inb = rl(own, f);
@@ -922,16 +958,19 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
   constexpr int NJ = 4 * U;
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t kmax = (uint32_t)a.k;
-  uint32_t* bm = (uint32_t*)smem;                       // [kBmWords] filter
-  uint32_t* tsk = bm + kBmWords;                         // [kTs] suspect ids
-  uint32_t* tsc = tsk + kTs;                             // [kTs] their counts
-  uint32_t* susp = tsc + kTs;                            // [kSusp] suspect list
-  uint4* tinfo = reinterpret_cast<uint4*>(susp + kSusp); // [L]
-  uint32_t* un = reinterpret_cast<uint32_t*>(tinfo + a.L);
-  uint32_t* marks = un;                                  // [W] window marks
-  uint32_t* bins = un;                                   // [kNB] radix bins
-  uint32_t* cutb = un + kNB;                             // [kCut] ids of the cut bin
-  uint32_t* surv = un + kNB + kCut;                      // [kmax] survivor keys
+  const uint32_t k4 = (kmax + 3u) & ~3u;
+  uint32_t* bm = (uint32_t*)smem;                         // [kBmWords] filter
+  uint32_t* tsk = bm + kBmWords;                           // [kTs] suspect ids
+  uint32_t* tsc = tsk + kTs;                               // [kTs] their counts
+  uint4* tinfo = reinterpret_cast<uint4*>(tsc + kTs);     // [L]
+  uint32_t* bins = reinterpret_cast<uint32_t*>(tinfo + a.L);  // [kNB] radix bins
+  uint32_t* cutb = bins + kNB;                             // [kCut] ids of the cut bin
+  uint16_t* marks = reinterpret_cast<uint16_t*>(bins);    // [W] window marks (table + 1; 0: none)
+  uint32_t* susp = bins + kNB - kSusp;                     // [kSusp] suspect list
+  uint32_t* b2 = bm + kBmWords - kB2Words;                 // [kB2Words] the suspects' filter
+  const bool staged = kmax <= kStageK;                     // output rows assembled in bm[0, 2k)
+  uint32_t* surv = staged ? bm + 512 : cutb + kCut;        // [kmax] survivor keys / ids of count >= 2
+  uint32_t* grp = surv + k4;                               // [kmax] ties grouped by bin
 
   const uint32_t lane = threadIdx.x;
   const uint32_t L = (uint32_t)a.L;
@@ -940,12 +979,13 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
   const uint32_t idshift = 32u - cb;
   const uint32_t idmask = (idshift >= 32) ? 0xFFFFFFFFu : ((1u << idshift) - 1u);
   uint4* bm4 = reinterpret_cast<uint4*>(bm);
+  uint4* bins4 = reinterpret_cast<uint4*>(bins);
   for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
   for (uint32_t i = lane; i < kTs; i += kWave) {
     tsk[i] = kEmpty;
     tsc[i] = 0;
   }
-  for (uint32_t i = lane; i < (uint32_t)W; i += kWave) marks[i] = kEmpty;
+  for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave) bins4[i] = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
   uint32_t ovf_buf = 0, ovf_n = 0;
@@ -1005,13 +1045,22 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
     const bool touched = !hand_on;
     uint32_t idv[NJ];
     uint32_t nsus = 0;
+    // radix bins of the first level (filled with the count-1 ids below): 511
+    // bins over [0, wid), sized so that about twice the share of ids
+    // expected below the cut (ids spread evenly, cut near k) is covered, and
+    // bin 511 for every id above
+    const uint64_t span = (uint64_t)(a.n_indexed > 0 ? a.n_indexed : 1);
+    uint64_t est = total > k ? 2ull * k * span / total + 64 : span;
+    if (est > span) est = span;
+    uint32_t s0 = bitlen64(est - 1) > 9 ? bitlen64(est - 1) - 9 : 0;
+    const uint32_t wid0 = (uint32_t)(kNB - 1) << s0;
     if (!hand_on) {
       // 2. gather every candidate (the tasks fit one window); an absent or
       // excluded candidate becomes kEmpty
 #pragma unroll
       for (int c = 0; c < LCH; ++c) {
         const uint32_t t = (uint32_t)c * 64 + lane;
-        if (tcnt[c] > 0 && tstart[c] > 0) marks[tstart[c]] = t;
+        if (tcnt[c] > 0 && tstart[c] > 0) marks[tstart[c]] = (uint16_t)(t + 1);
       }
       uint32_t tf = 0;
 #pragma unroll
@@ -1019,16 +1068,20 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
         const uint64_t bal = __ballot(tcnt[c] > 0 && tstart[c] == 0);
         if (bal) tf = (uint32_t)c * 64 + (uint32_t)__ffsll((unsigned long long)bal) - 1;
       }
-      if (lane == 0) marks[0] = tf;
+      if (lane == 0) marks[0] = (uint16_t)(tf + 1);
       wave_lds_sync();
+      // every task's 16-byte load is issued before any is used
       uint32_t tcarry = 0;
+      uint4 v4[U];
+      uint32_t vm[U];
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        idv[4 * u + 0] = idv[4 * u + 1] = idv[4 * u + 2] = idv[4 * u + 3] = kEmpty;
+        vm[u] = 0;
+        v4[u] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
         if ((uint32_t)u * kWave < n_tasks) {
           const uint32_t mk = marks[u * kWave + lane];
-          marks[u * kWave + lane] = kEmpty;
-          uint32_t tt = wave_incl_max(mk == kEmpty ? 0u : mk + 1);
+          marks[u * kWave + lane] = 0;
+          uint32_t tt = wave_incl_max(mk);   // table + 1 of the latest mark at or before this task
           tt = tt > tcarry ? tt : tcarry;
           tcarry = rl(tt, 63);
           const uint32_t task = (uint32_t)u * kWave + lane;
@@ -1036,22 +1089,24 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
           const uint4 ti = tinfo[tt - 1];
           const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
           const uint32_t room = ti.z - 4u * tc;
-          const uint32_t vm = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
-          uint4 v4;
+          vm[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
           if (ALIGNED) {
-            v4 = *reinterpret_cast<const uint4*>(a.ids + addr);
+            v4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
           } else {
             const uint32_t last = room - 1;
-            v4.x = (uint32_t)a.ids[addr];
-            v4.y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
-            v4.z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
-            v4.w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
+            v4[u].x = (uint32_t)a.ids[addr];
+            v4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
+            v4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
+            v4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
           }
-          const uint32_t vv[4] = {v4.x, v4.y, v4.z, v4.w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            idv[4 * u + i] = (((vm >> i) & 1u) && (int64_t)vv[i] != self) ? vv[i] : kEmpty;
         }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const uint32_t vv[4] = {v4[u].x, v4[u].y, v4[u].z, v4[u].w};
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          idv[4 * u + i] = (((vm[u] >> i) & 1u) && (int64_t)vv[i] != self) ? vv[i] : kEmpty;
       }
       load_counts();
       // 3a. filter: a candidate whose bit is already set is a suspect
@@ -1082,11 +1137,14 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
     if (!touched) load_counts();
     uint32_t nmulti = 0, nsing = 0;
     if (!hand_on) {
+      if (nsus) reinterpret_cast<uint4*>(b2)[lane] = make_uint4(0, 0, 0, 0);   // the filter's last words
       wave_lds_sync();
       // 3b. the suspects into the exact table (ids only; linear probing, at
-      // most half full)
+      // most half full), and their bits into the suspects' filter
       for (uint32_t i = lane; i < nsus; i += kWave) {
         const uint32_t x = susp[i];
+        const uint32_t h2 = b2_bit(x);
+        atomicOr(&b2[h2 >> 5], 1u << (h2 & 31u));
         uint32_t sl = ts_slot(x);
         for (;;) {
           const uint32_t o = atomicCAS(&tsk[sl], kEmpty, x);
@@ -1095,42 +1153,56 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
         }
       }
       wave_lds_sync();
+      // the suspect list sits in the bins, which count from here on
+      if (nsus && lane < kSusp / 4) reinterpret_cast<uint4*>(susp)[lane] = make_uint4(0, 0, 0, 0);
+      wave_lds_sync();
       // 3c. count every candidate that is a suspect; the others occur once
+      // and go into the first level's radix bins
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if ((uint32_t)u * kWave < n_tasks) {
-          uint32_t sl[4], o[4];
+          uint32_t sl[4], o[4], f2[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const uint32_t h2 = b2_bit(idv[4 * u + i]);
+            f2[i] = (nsus && idv[4 * u + i] != kEmpty) ? (b2[h2 >> 5] >> (h2 & 31u)) & 1u : 0u;
+          }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             sl[i] = ts_slot(idv[4 * u + i]);
-            o[i] = idv[4 * u + i] != kEmpty ? tsk[sl[i]] : kEmpty;
+            o[i] = f2[i] ? tsk[sl[i]] : kEmpty;
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const uint32_t x = idv[4 * u + i];
-            if (x != kEmpty && o[i] != kEmpty) {
-              uint32_t s2 = sl[i], o2 = o[i];
-              while (o2 != x && o2 != kEmpty) {
+            uint32_t s2 = sl[i], o2 = o[i];
+            if (o2 != x && o2 != kEmpty) {   // another id holds the slot: walk on
+              do {
                 s2 = (s2 + 1) & (kTs - 1);
                 o2 = tsk[s2];
-              }
-              if (o2 == x) {
-                atomicAdd(&tsc[s2], 1u);
-                idv[4 * u + i] = kEmpty;
-              }
+              } while (o2 != x && o2 != kEmpty);
             }
-            nsing += (uint32_t)__popcll(__ballot(idv[4 * u + i] != kEmpty));
+            const bool hit = o2 == x && x != kEmpty;
+            if (hit) atomicAdd(&tsc[s2], 1u);
+            const uint32_t y = hit ? kEmpty : x;
+            idv[4 * u + i] = y;
+            if (y < wid0) atomicAdd(&bins[y >> s0], 1u);   // the ids above are counted as a remainder
+            nsing += (uint32_t)__popcll(__ballot(y != kEmpty));
           }
         }
       }
       wave_lds_sync();
-      // the table's ids of count >= 2, and of count 1 (they occur once:
-      // their bit was set by another id)
+      // the table's ids of count >= 2, and of count 1 (they occur once: their
+      // bit was set by another id; they join the bins)
       uint32_t nm = 0, n1 = 0;
-      for (uint32_t i = lane; i < kTs; i += kWave) {
-        const uint32_t c = tsk[i] != kEmpty ? tsc[i] : 0u;
-        nm += c >= 2;
-        n1 += c == 1;
+      if (nsus) {
+        for (uint32_t i = lane; i < kTs; i += kWave) {
+          const uint32_t x = tsk[i];
+          const uint32_t c = x != kEmpty ? tsc[i] : 0u;
+          nm += c >= 2;
+          n1 += c == 1;
+          if (c == 1 && x < wid0) atomicAdd(&bins[x >> s0], 1u);
+        }
       }
       nmulti = wave_sum(nm);
       nsing += wave_sum(n1);
@@ -1140,132 +1212,212 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
       if (lane == ovf_n) ovf_buf = (uint32_t)q;
       if (++ovf_n == (uint32_t)kWave) ovf_n = flush_overflow(a, ovf_buf, ovf_n);
     } else {
-      // 4. ids of count >= 2 all survive; then the `need` smallest ids of
-      // count 1: ids below x_lo, and the smallest `cut` of [x_lo, x_hi)
+      // 4. the ids of count >= 2 all survive, ahead of the rest; then the
+      // `need` smallest ids of count 1
       const uint32_t D = nsing + nmulti;
       const uint32_t need = (D <= k ? D : k) - nmulti;
-      // ranges in 32 bits: ids are below 2^31, so 0xFFFFFFFF stands for 2^32
-      uint32_t x_lo = kEmpty, x_hi = kEmpty;
-      uint32_t cut = 0;
-      if (need < nsing) {
-        const uint64_t span = (uint64_t)(a.n_indexed > 0 ? a.n_indexed : 1);
-        uint64_t est = 2ull * need * span / nsing + 64;
-        if (est > span) est = span;
-        uint32_t s = bitlen64(est - 1) > 9 ? bitlen64(est - 1) - 9 : 0;
-        // level 0 covers [0, 511 << s) and bin 511 takes the ids above; a
-        // deeper level covers the cut bin [lo, lo + wid) of the level before
-        uint32_t lo = 0, wid = (uint32_t)(kNB - 1) << s;
-        uint32_t needl = need;
-        for (int level = 0;; ++level) {
-          for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave)
-            reinterpret_cast<uint4*>(bins)[i] = make_uint4(0, 0, 0, 0);
-          wave_lds_sync();
-          auto bin_of = [&](uint32_t x) {
-            const uint32_t d = x - lo;   // wraps above wid for x < lo (lo + wid <= 2^32)
-            if (x != kEmpty) {
-              if (d < wid) atomicAdd(&bins[d >> s], 1u);
-              else if (level == 0) atomicAdd(&bins[kNB - 1], 1u);
-            }
-          };
-#pragma unroll
-          for (int u = 0; u < U; ++u)
-            if ((uint32_t)u * kWave < n_tasks) {
-#pragma unroll
-              for (int i = 0; i < 4; ++i) bin_of(idv[4 * u + i]);
-            }
-          for (uint32_t i = lane; i < kTs; i += kWave) bin_of(tsc[i] == 1 ? tsk[i] : kEmpty);
-          wave_lds_sync();
-          uint32_t before, inb;
-          const uint32_t bs = find_cut_bin(bins, needl, &before, &inb);
-          uint32_t nlo, nwid;
-          if (level == 0 && bs == (uint32_t)kNB - 1) {
-            nlo = wid;
-            nwid = kEmpty - wid;   // [wid, 2^32)
-          } else {
-            nlo = lo + (bs << s);
-            const uint32_t rest = wid - (bs << s);
-            nwid = (1u << s) < rest ? (1u << s) : rest;
-          }
-          needl -= before;
-          // each level narrows the range 2^9-fold: ids below 2^32 need at
-          // most four levels; the bound only guards the loop
-          if (inb <= kCut || level >= 5) {
-            x_lo = nlo;
-            x_hi = nlo + nwid;
-            if (x_hi < nlo) x_hi = kEmpty;
-            cut = needl;
-            break;
-          }
-          lo = nlo;
-          wid = nwid;
-          s = bitlen64(wid - 1) > 9 ? bitlen64(wid - 1) - 9 : 0;
-          wave_lds_sync();
-        }
-      }
-      // survivor keys: count >= 2, then count-1 ids below x_lo, then the
-      // ranked cut bin
-      uint32_t m = 0, ncut = 0;
-      for (uint32_t i0 = 0; i0 < kTs; i0 += kWave) {
-        const uint32_t x = tsk[i0 + lane];
-        const uint32_t c = x != kEmpty ? tsc[i0 + lane] : 0u;
-        const bool mult = c >= 2, one = c == 1;
-        const bool all = one && x < x_lo;
-        const bool part = one && x >= x_lo && x < x_hi;
-        const uint64_t mm = __ballot(mult || all);
-        if (mult || all) surv[m + mbcnt(mm)] = ((L - (mult ? c : 1u)) << idshift) | x;
-        m += (uint32_t)__popcll(mm);
-        const uint64_t mp = __ballot(part);
-        if (part && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = x;
-        ncut += (uint32_t)__popcll(mp);
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        if ((uint32_t)u * kWave < n_tasks) {
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const uint32_t x = idv[4 * u + i];
-            const bool all = x < x_lo;   // kEmpty never passes
-            const bool part = x != kEmpty && x >= x_lo && x < x_hi;
-            const uint64_t mm = __ballot(all);
-            if (all) surv[m + mbcnt(mm)] = ((L - 1u) << idshift) | x;
-            m += (uint32_t)__popcll(mm);
-            const uint64_t mp = __ballot(part);
-            if (mp) {
-              if (part && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = x;
-              ncut += (uint32_t)__popcll(mp);
-            }
-          }
-        }
-      }
-      wave_lds_sync();
-      if (ncut > kCut) ncut = kCut;   // not reached: the cut bin holds at most kCut ids
-      if (ncut) {
-        const uint32_t mine = lane < ncut ? cutb[lane] : 0u;
-        uint32_t rank = 0;
-        for (uint32_t j = 0; j < ncut; ++j) rank += cutb[j] < mine;
-        const bool sel = lane < ncut && rank < cut;
-        const uint64_t mm = __ballot(sel);
-        if (sel) surv[m + mbcnt(mm)] = ((L - 1u) << idshift) | mine;
-        m += (uint32_t)__popcll(mm);
-        wave_lds_sync();
-      }
       const uint64_t orow = q * (uint64_t)kmax;
-      for (uint32_t j = k + lane; j < kmax; j += kWave) {
-        a.out_ids[orow + j] = -1;
-        a.out_counts[orow + j] = 0;
-      }
-      if (m <= 64) {
-        sort_write<1>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
-      } else if (m <= 128) {
-        sort_write<2>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
-      } else if (m <= 256) {
-        sort_write<4>(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+      int32_t* oid = a.out_ids + orow;
+      int32_t* ocnt = a.out_counts + orow;
+      wave_lds_sync();
+      uint32_t bstar = 0, before = 0, inb = 0;
+      if (need < nsing) bstar = find_cut_bin(bins, need, &before, &inb, true, nsing);
+      if (need < nsing && inb <= kCut && bstar < (uint32_t)kNB - 1) {
+        // 5a. one radix level settles it: the ties of bins below b* survive,
+        // and the smallest `need - before` of bin b*.  Output place of a
+        // survivor = ids of count >= 2 + the start of its bin's group + its
+        // rank in the group (bins are id ranges), so no sort is needed.
+        // The bins below b* now hold the start of their groups; scattering
+        // advances each to the group's end.
+        uint32_t ncut = 0;
+        auto place = [&](uint32_t y) {
+          const uint32_t b = y < wid0 ? y >> s0 : (uint32_t)(kNB - 1);
+          const bool lowbin = y != kEmpty && b < bstar;
+          const bool inbin = y != kEmpty && b == bstar;
+          if (lowbin) grp[atomicAdd(&bins[b], 1u)] = y;
+          const uint64_t mp = __ballot(inbin);
+          if (mp) {
+            if (inbin && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = y;
+            ncut += (uint32_t)__popcll(mp);
+          }
+        };
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if ((uint32_t)u * kWave < n_tasks) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) place(idv[4 * u + i]);
+          }
+        uint32_t nmc = 0;
+        if (nsus) {
+          for (uint32_t i0 = 0; i0 < kTs; i0 += kWave) {
+            const uint32_t x = tsk[i0 + lane];
+            const uint32_t c = x != kEmpty ? tsc[i0 + lane] : 0u;
+            place(c == 1 ? x : kEmpty);
+            // ids of count >= 2: key (L - count, id)
+            const bool mult = c >= 2;
+            const uint64_t mm = __ballot(mult);
+            if (mult) surv[nmc + mbcnt(mm)] = ((L - c) << idshift) | x;
+            nmc += (uint32_t)__popcll(mm);
+          }
+        }
+        wave_lds_sync();
+        // each survivor's place is known: the row is assembled in the first
+        // filter's words (free now; ids, then counts) and stored with
+        // coalesced writes, or written in place when k is above 512
+        auto put = [&](uint32_t pos, uint32_t id, uint32_t cnt) {
+          if (staged) {
+            bm[pos] = id;
+            bm[kmax + pos] = cnt;
+          } else {
+            oid[pos] = (int32_t)id;
+            ocnt[pos] = (int32_t)cnt;
+          }
+        };
+        // ids of count >= 2: rank among themselves by (count desc, id asc)
+        for (uint32_t j0 = 0; j0 < nmulti; j0 += kWave) {
+          const uint32_t j = j0 + lane;
+          const uint32_t key = j < nmulti ? surv[j] : 0xFFFFFFFFu;
+          uint32_t rank = 0;
+          for (uint32_t i = 0; i < nmulti; ++i) rank += surv[i] < key;
+          if (j < nmulti) put(rank, key & idmask, L - (key >> idshift));
+        }
+        // ties below the cut bin: rank inside the bin's group
+        for (uint32_t p = lane; p < before; p += kWave) {
+          const uint32_t y = grp[p];
+          const uint32_t b = y >> s0;   // below the cut bin: y < wid0
+          const uint32_t g0 = b ? bins[b - 1] : 0u, g1 = bins[b];
+          uint32_t rank = 0;
+          for (uint32_t i = g0; i < g1; ++i) rank += grp[i] < y;
+          put(nmulti + g0 + rank, y, 1u);
+        }
+        // the cut bin: its `need - before` smallest
+        if (lane < ncut) {
+          const uint32_t y = cutb[lane];
+          uint32_t rank = 0;
+          for (uint32_t i = 0; i < ncut; ++i) rank += cutb[i] < y;
+          if (rank < need - before) put(nmulti + before + rank, y, 1u);
+        }
+        const uint32_t m = nmulti + need;
+        if (staged) {
+          wave_lds_sync();
+          for (uint32_t j = lane; j < kmax; j += kWave) {
+            oid[j] = j < m ? (int32_t)bm[j] : -1;
+            ocnt[j] = j < m ? (int32_t)bm[kmax + j] : 0;
+          }
+        } else {
+          for (uint32_t j = m + lane; j < kmax; j += kWave) {
+            oid[j] = -1;
+            ocnt[j] = 0;
+          }
+        }
       } else {
-        rank_write(surv, m, k, L, idshift, idmask, a.out_ids + orow, a.out_counts + orow);
+        // 5b. all ids of count 1 survive, or the cut needs finer bins:
+        // ids below x_lo survive with the smallest `cut` of [x_lo, x_hi),
+        // found level by level (32-bit ranges: ids are below 2^31, so
+        // 0xFFFFFFFF stands for 2^32), then every survivor key is sorted
+        uint32_t x_lo = kEmpty, x_hi = kEmpty;
+        uint32_t cut = 0;
+        if (need < nsing) {
+          uint32_t s = s0, lo = 0, wid = wid0, needl = need;
+          uint32_t bs = bstar, bef = before, in_b = inb;
+          for (int level = 0;; ++level) {
+            if (level > 0) {
+              for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave) bins4[i] = make_uint4(0, 0, 0, 0);
+              wave_lds_sync();
+              auto bin_of = [&](uint32_t x) {
+                const uint32_t d = x - lo;   // wraps above wid for x < lo (lo + wid <= 2^32)
+                if (x != kEmpty && d < wid) atomicAdd(&bins[d >> s], 1u);
+              };
+#pragma unroll
+              for (int u = 0; u < U; ++u)
+                if ((uint32_t)u * kWave < n_tasks) {
+#pragma unroll
+                  for (int i = 0; i < 4; ++i) bin_of(idv[4 * u + i]);
+                }
+              if (nsus)
+                for (uint32_t i = lane; i < kTs; i += kWave) bin_of(tsc[i] == 1 ? tsk[i] : kEmpty);
+              wave_lds_sync();
+              bs = find_cut_bin(bins, needl, &bef, &in_b, false);
+            }
+            uint32_t nlo, nwid;
+            if (level == 0 && bs == (uint32_t)kNB - 1) {
+              nlo = wid;
+              nwid = kEmpty - wid;   // [wid, 2^32)
+            } else {
+              nlo = lo + (bs << s);
+              const uint32_t rest = wid - (bs << s);
+              nwid = (1u << s) < rest ? (1u << s) : rest;
+            }
+            needl -= bef;
+            // each level narrows the range 2^9-fold: ids below 2^32 need at
+            // most four levels; the bound only guards the loop
+            if (in_b <= kCut || level >= 5) {
+              x_lo = nlo;
+              x_hi = nlo + nwid;
+              if (x_hi < nlo) x_hi = kEmpty;
+              cut = needl;
+              break;
+            }
+            lo = nlo;
+            wid = nwid;
+            s = bitlen64(wid - 1) > 9 ? bitlen64(wid - 1) - 9 : 0;
+            wave_lds_sync();
+          }
+        }
+        uint32_t m = 0, ncut = 0;
+        auto take = [&](uint32_t x, uint32_t c) {
+          const bool all = x != kEmpty && (c >= 2 || x < x_lo);
+          const bool part = x != kEmpty && c == 1 && x >= x_lo && x < x_hi;
+          const uint64_t mm = __ballot(all);
+          if (all) surv[m + mbcnt(mm)] = ((L - c) << idshift) | x;
+          m += (uint32_t)__popcll(mm);
+          const uint64_t mp = __ballot(part);
+          if (mp) {
+            if (part && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = x;
+            ncut += (uint32_t)__popcll(mp);
+          }
+        };
+        if (nsus)
+          for (uint32_t i0 = 0; i0 < kTs; i0 += kWave) {
+            const uint32_t x = tsk[i0 + lane];
+            take(x, x != kEmpty ? tsc[i0 + lane] : 0u);
+          }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+          if ((uint32_t)u * kWave < n_tasks) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) take(idv[4 * u + i], 1u);
+          }
+        wave_lds_sync();
+        if (ncut > kCut) ncut = kCut;   // not reached: the cut bin holds at most kCut ids
+        if (ncut) {
+          const uint32_t mine = lane < ncut ? cutb[lane] : 0u;
+          uint32_t rank = 0;
+          for (uint32_t j = 0; j < ncut; ++j) rank += cutb[j] < mine;
+          const bool sel = lane < ncut && rank < cut;
+          const uint64_t mm = __ballot(sel);
+          if (sel) surv[m + mbcnt(mm)] = ((L - 1u) << idshift) | mine;
+          m += (uint32_t)__popcll(mm);
+          wave_lds_sync();
+        }
+        for (uint32_t j = k + lane; j < kmax; j += kWave) {
+          oid[j] = -1;
+          ocnt[j] = 0;
+        }
+        if (m <= 64) {
+          sort_write<1>(surv, m, k, L, idshift, idmask, oid, ocnt);
+        } else if (m <= 128) {
+          sort_write<2>(surv, m, k, L, idshift, idmask, oid, ocnt);
+        } else if (m <= 256) {
+          sort_write<4>(surv, m, k, L, idshift, idmask, oid, ocnt);
+        } else {
+          rank_write(surv, m, k, L, idshift, idmask, oid, ocnt);
+        }
       }
     }
-    // 5. leave the filter, the suspect table and the window marks
-    // (overwritten by the selection buffers) empty for the next query
+    // 6. leave the filter, the suspect table, the bins and the marks empty
+    // for the next query (the marks were cleared as they were read; clearing
+    // them all again costs one store per lane)
     wave_lds_sync();
     if (touched) {
       for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
@@ -1273,7 +1425,7 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
         reinterpret_cast<uint4*>(tsk)[lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
         reinterpret_cast<uint4*>(tsc)[lane] = make_uint4(0, 0, 0, 0);
       }
-      for (uint32_t i = lane; i < (uint32_t)W; i += kWave) marks[i] = kEmpty;
+      for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave) bins4[i] = make_uint4(0, 0, 0, 0);
     }
     wave_lds_sync();
   }
