@@ -874,25 +874,27 @@ static_assert(kMarkWords <= (uint32_t)kNB, "the window marks live in the radix b
 // no suspect, so only about one in a hundred probes the suspect table
 constexpr uint32_t kB2Words = 256;
 constexpr uint32_t kStageK = 256;   // rows of up to this k are assembled in LDS
+constexpr uint32_t kSmallK = 128;   // up to this k the survivor keys fit the suspects' filter's words
+static_assert(256 + 2 * kTs + kB2Words == kBmWords, "suspect table and suspects' filter fill the filter's words");
 static_assert(kSusp <= (uint32_t)kNB - kMarkWords, "the suspect list follows the marks in the bins");
 
-// LDS words: filter, suspect ids and counts, table info, radix bins, the cut
-// bin's ids, and (k above kStageK only) survivor keys and tie groups.  Buffers
-// whose lifetimes do not overlap share words:
+// LDS words: filter, table info, radix bins, the cut bin's ids, and (k above
+// kSmallK only) survivor keys and tie groups.  Buffers whose lifetimes do not
+// overlap share words:
 //   - the window marks (gather) are the first bins: once read they are zero
 //     again, as the bins must be when counting starts;
 //   - the suspect list (filter, suspect table) is the last 128 bins, cleared
 //     after use;
-//   - the suspects' filter (suspect table, lookup) is the last 256 words of
-//     the first filter, free once every candidate has passed it (cleared
-//     before use);
+//   - once every candidate has passed the filter its words are free: words
+//     256..767 hold the suspect table (ids, then counts) and 768..1023 the
+//     suspects' filter, both set up before use; with k <= kSmallK the survivor
+//     keys and tie groups then take the suspects' filter's words;
 //   - with k <= kStageK the output row (ids, then counts) is assembled in the
-//     first filter's first 2k words, and the survivor keys and tie groups
-//     follow at word 512.
-// Everything is zero (filters, bins) or empty (suspect table) between queries.
+//     first 2k words once the suspect table has been read for the last time.
+// The filter and the bins are zero between queries.
 __host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
   const uint32_t k4 = (kmax + 3u) & ~3u;
-  return kBmWords + 2 * kTs + 4u * (uint32_t)L + (uint32_t)kNB + kCut + (kmax <= kStageK ? 0u : 2 * k4);
+  return kBmWords + 4u * (uint32_t)L + (uint32_t)kNB + kCut + (kmax <= kSmallK ? 0u : 2 * k4);
 }
 
 __device__ __forceinline__ uint32_t filter_bit(uint32_t id) { return (id * 0x9E3779B1u) >> 17; }
@@ -952,7 +954,9 @@ __device__ __forceinline__ uint32_t find_cut_bin(uint32_t* bins, uint32_t need, 
 __device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64u - (uint32_t)__clzll((long long)x) : 0u; }
 
 template <int LCH, bool ALIGNED>
-__global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
+// At most 96 VGPRs (five waves per SIMD): the stage waits on memory, and
+// 20 waves per CU keep more loads in flight than 16 with fewer spills.
+__global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
   constexpr int U = kFastU;
   constexpr int W = kWave * U;
   constexpr int NJ = 4 * U;
@@ -960,16 +964,16 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
   const uint32_t kmax = (uint32_t)a.k;
   const uint32_t k4 = (kmax + 3u) & ~3u;
   uint32_t* bm = (uint32_t*)smem;                         // [kBmWords] filter
-  uint32_t* tsk = bm + kBmWords;                           // [kTs] suspect ids
+  uint32_t* tsk = bm + 256;                                // [kTs] suspect ids
   uint32_t* tsc = tsk + kTs;                               // [kTs] their counts
-  uint4* tinfo = reinterpret_cast<uint4*>(tsc + kTs);     // [L]
+  uint4* tinfo = reinterpret_cast<uint4*>(bm + kBmWords);  // [L]
   uint32_t* bins = reinterpret_cast<uint32_t*>(tinfo + a.L);  // [kNB] radix bins
   uint32_t* cutb = bins + kNB;                             // [kCut] ids of the cut bin
   uint16_t* marks = reinterpret_cast<uint16_t*>(bins);    // [W] window marks (table + 1; 0: none)
   uint32_t* susp = bins + kNB - kSusp;                     // [kSusp] suspect list
   uint32_t* b2 = bm + kBmWords - kB2Words;                 // [kB2Words] the suspects' filter
   const bool staged = kmax <= kStageK;                     // output rows assembled in bm[0, 2k)
-  uint32_t* surv = staged ? bm + 512 : cutb + kCut;        // [kmax] survivor keys / ids of count >= 2
+  uint32_t* surv = kmax <= kSmallK ? b2 : cutb + kCut;    // [kmax] survivor keys / ids of count >= 2
   uint32_t* grp = surv + k4;                               // [kmax] ties grouped by bin
 
   const uint32_t lane = threadIdx.x;
@@ -981,10 +985,6 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
   uint4* bm4 = reinterpret_cast<uint4*>(bm);
   uint4* bins4 = reinterpret_cast<uint4*>(bins);
   for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
-  for (uint32_t i = lane; i < kTs; i += kWave) {
-    tsk[i] = kEmpty;
-    tsc[i] = 0;
-  }
   for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave) bins4[i] = make_uint4(0, 0, 0, 0);
   __syncthreads();
 
@@ -1137,7 +1137,12 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
     if (!touched) load_counts();
     uint32_t nmulti = 0, nsing = 0;
     if (!hand_on) {
-      if (nsus) reinterpret_cast<uint4*>(b2)[lane] = make_uint4(0, 0, 0, 0);   // the filter's last words
+      if (nsus) {
+        // the suspect table and the suspects' filter take the filter's words
+        reinterpret_cast<uint4*>(tsk)[lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+        reinterpret_cast<uint4*>(tsc)[lane] = make_uint4(0, 0, 0, 0);
+        reinterpret_cast<uint4*>(b2)[lane] = make_uint4(0, 0, 0, 0);
+      }
       wave_lds_sync();
       // 3b. the suspects into the exact table (ids only; linear probing, at
       // most half full), and their bits into the suspects' filter
@@ -1421,10 +1426,6 @@ __global__ __launch_bounds__(64) void count_topk_fast_kernel(QueryArgs a) {
     wave_lds_sync();
     if (touched) {
       for (uint32_t i = lane; i < kBmWords / 4; i += kWave) bm4[i] = make_uint4(0, 0, 0, 0);
-      if (nsus) {
-        reinterpret_cast<uint4*>(tsk)[lane] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
-        reinterpret_cast<uint4*>(tsc)[lane] = make_uint4(0, 0, 0, 0);
-      }
       for (uint32_t i = lane; i < (uint32_t)kNB / 4; i += kWave) bins4[i] = make_uint4(0, 0, 0, 0);
     }
     wave_lds_sync();
