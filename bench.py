@@ -195,10 +195,11 @@ def main():
                   "occupied_ids_per_query": round(occ_sum / n, 1)},
     }
     dom = max(("hash", "query"), key=lambda x: phases[x]["ms"])
-    kernel = {"hash": "doph_hash_kernel", "query": "count_topk_kernel"}[dom]
+    kernel = {"hash": "doph_hash_kernel", "query": "count_topk"}[dom]
     achieved = phases[dom]["alg_bytes"] / (phases[dom]["ms"] * 1e6)
     traffic = _traffic(args.traffic_table, args.workload, kernel)
-    roofline = {"bound": "hbm", "kernel": kernel + (" (all table-size stages)" if dom == "query" else ""),
+    roofline = {"bound": "hbm",
+                "kernel": kernel + (" kernels (filter stage + counting-table stages)" if dom == "query" else ""),
                 "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic}
