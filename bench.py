@@ -108,7 +108,8 @@ def main():
 
     p = flash.flash_params.make(K, L, b, R, seed=1)
     M = p.M
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
+    counts = flash.index_parts(p, index)[0]     # each reservoir's header word
     keys = torch.empty(n * L, dtype=torch.int32, device="cuda")
     ins_ws = flash.alloc_workspace(flash.OP_INSERT, p, n_rows=n)
     q_ws = flash.alloc_workspace(flash.OP_QUERY_KEYS, p, n_queries=n, k=k)
@@ -121,9 +122,9 @@ def main():
         ev[0].record(stream)
         flash.flash_hash(p, rp, ci, keys, stream=stream)
         ev[1].record(stream)
-        flash.flash_insert_keys(p, keys, counts, ids, ins_ws, stream=stream)
+        flash.flash_insert_keys(p, keys, index, ins_ws, stream=stream)
         ev[2].record(stream)
-        flash.flash_query_keys(p, counts, ids, n, keys, k, oi, oc, q_ws, self_ids=self_ids,
+        flash.flash_query_keys(p, index, n, keys, k, oi, oc, q_ws, self_ids=self_ids,
                                stream=stream)
         ev[3].record(stream)
 
@@ -143,8 +144,8 @@ def main():
 
     def gstep():
         flash.flash_hash(p, rp, ci, keys, stream=gs)
-        flash.flash_insert_keys(p, keys, counts, ids, ins_ws, stream=gs)
-        flash.flash_query_keys(p, counts, ids, n, keys, k, oi, oc, q_ws, self_ids=self_ids, stream=gs)
+        flash.flash_insert_keys(p, keys, index, ins_ws, stream=gs)
+        flash.flash_query_keys(p, index, n, keys, k, oi, oc, q_ws, self_ids=self_ids, stream=gs)
 
     gs.wait_stream(stream)
     graph = torch.cuda.CUDAGraph()
@@ -168,7 +169,7 @@ def main():
 
     # algorithmic bytes per launch
     kq = keys.view(n, L).long() & 0xFFFFFFFF
-    cnt = counts.view(L, M).long()
+    cnt = counts.reshape(L, M).long()
     occ = torch.clamp(cnt[torch.arange(L, device="cuda")[None, :], kq.clamp(0, M - 1)], max=R)
     occ = torch.where(kq < M, occ, torch.zeros_like(occ))   # empty rows' keys hit no bucket
     occ_sum = int(occ.sum().item())
@@ -179,7 +180,7 @@ def main():
            (per_q > 2048).float().mean().item()))
     bytes_hash = 4 * nnz + 8 * (n + 1) + 4 * n * L
     # insert: read the keys (4 B per insertion), stage an (id, priority)
-    # pair per insertion (12 B), write the counts (4 B per bucket) and the
+    # pair per insertion (12 B), write every reservoir's header (4 B) and the
     # kept ids (4 B per occupied slot)
     n_ins = int((kq < M).sum().item())
     nb = L * M
@@ -276,9 +277,9 @@ def _url_serving_setup(rows_override=0, pool_n=400_000):
     t0 = time.time()
     rp, ci = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
-    flash.flash_build_index(p, rp, ci, counts, ids, ws)
+    flash.flash_build_index(p, rp, ci, index, ws)
     torch.cuda.synchronize()
     del ws
     log(f"url-shaped index: {spec.n_rows} rows, {int(ci.numel())} nnz, built in {time.time() - t0:.1f}s")
@@ -291,7 +292,7 @@ def _url_serving_setup(rows_override=0, pool_n=400_000):
         a, b = int(qrp[st]), int(qrp[st + n])
         return (qrp[st:st + n + 1] - a).astype(np.int64), qci[a:b].copy()
 
-    return {"spec": spec, "p": p, "counts": counts, "ids": ids, "rp": rp, "ci": ci,
+    return {"spec": spec, "p": p, "index": index, "rp": rp, "ci": ci,
             "rows": rows, "qrp": qrp, "qci": qci, "pool_n": pool_n}
 
 
@@ -309,7 +310,7 @@ def _serving_rates(env, rates, n_requests, warmup, repeats, slots, budget):
     from paper_1709_01190_amd import serving
 
     rows = env["rows"]
-    ex = serving.GpuExecutor(env["p"], env["counts"], env["ids"], env["spec"].n_rows)
+    ex = serving.GpuExecutor(env["p"], env["index"], env["spec"].n_rows)
     cont = serving.ContinuousServer(ex, budget_bytes=budget, slots=slots)
     batch = serving.BatchAllServer(ex, budget_bytes=budget)
     max_batch = 4096
@@ -361,7 +362,7 @@ def serving_bench(args):
 
     torch.cuda.set_device(0)
     env = _url_serving_setup(args.rows)
-    spec, p, counts, ids = env["spec"], env["p"], env["counts"], env["ids"]
+    spec, p, index = env["spec"], env["p"], env["index"]
     budget = 4 << 30
     rates = [float(x) for x in args.rates.split(",")]
     table = _serving_rates(env, rates, args.requests, args.serving_warmup, args.serving_repeats,
@@ -378,7 +379,7 @@ def serving_bench(args):
         oi = torch.empty(len(sel) * k, dtype=torch.int32, device="cuda")
         oc = torch.empty_like(oi)
         qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=len(sel), k=k)
-        flash.flash_query_batch(p, counts, ids, spec.n_rows, srp_d, sci_d, k, oi, oc, qws)
+        flash.flash_query_batch(p, index, spec.n_rows, srp_d, sci_d, k, oi, oc, qws)
         torch.cuda.synchronize()
         t1 = time.time()
         recall = recall_exact_jaccard(env["rp"], env["ci"], spec.n_cols, srp_d, sci_d, oi.view(len(sel), k))
@@ -428,14 +429,14 @@ def uneven_bench(args):
     torch.cuda.synchronize()
     log(f"click-log-shaped index rows: {spec.n_rows} rows, {int(ci.numel())} nnz in {time.time() - t0:.1f}s")
     p = flash.flash_params.make(K, L, b, R, seed=1)
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
     stream = torch.cuda.current_stream()
     build_ms = []
     for _ in range(3):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        flash.flash_build_index(p, rp, ci, counts, ids, ws, stream=stream)
+        flash.flash_build_index(p, rp, ci, index, ws, stream=stream)
         e1.record(stream)
         torch.cuda.synchronize()
         build_ms.append(e0.elapsed_time(e1))
@@ -470,7 +471,7 @@ def uneven_bench(args):
         return out
 
     def persistent():
-        flash.flash_query_batch_mixed(p, counts, ids, spec.n_rows, qrp, qci, kq, kmax, oi, oc, qws,
+        flash.flash_query_batch_mixed(p, index, spec.n_rows, qrp, qci, kq, kmax, oi, oc, qws,
                                       stream=stream)
 
     flash.flash_set_tuning(None)
@@ -482,7 +483,7 @@ def uneven_bench(args):
     soi = torch.empty(ns * kmax, dtype=torch.int32, device="cuda")
     soc = torch.empty_like(soi)
     sws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=ns, k=kmax)
-    best, best_ms = flash.flash_autotune_query_batch(p, counts, ids, spec.n_rows, srp, sci, kq[:ns].contiguous(),
+    best, best_ms = flash.flash_autotune_query_batch(p, index, spec.n_rows, srp, sci, kq[:ns].contiguous(),
                                                      kmax, soi, soc, sws, reps=2, stream=stream)
     log(f"autotuned on {ns} queries: {best.as_dict()} ({best_ms:.3f} ms)")
     timed(persistent, args.warmup)
@@ -510,7 +511,7 @@ def uneven_bench(args):
 
     def per_bucket():
         for sel, brp, bci, bk, boi, boc, bws in buckets:
-            flash.flash_query_batch(p, counts, ids, spec.n_rows, brp, bci, bk, boi, boc, bws, stream=stream)
+            flash.flash_query_batch(p, index, spec.n_rows, brp, bci, bk, boi, boc, bws, stream=stream)
 
     timed(per_bucket, args.warmup)
     bucket_ms = timed(per_bucket, args.steps)
@@ -568,7 +569,7 @@ def append_bench(args):
     rp, ci = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
     stream = torch.cuda.current_stream()
-    c1, i1 = flash.alloc_index(p)
+    index1 = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=n)
 
     def timed(fn, reps):
@@ -582,7 +583,7 @@ def append_bench(args):
             out.append(e0.elapsed_time(e1))
         return out
 
-    one = timed(lambda: flash.flash_build_index(p, rp, ci, c1, i1, ws, stream=stream), args.warmup + args.steps)
+    one = timed(lambda: flash.flash_build_index(p, rp, ci, index1, ws, stream=stream), args.warmup + args.steps)
     del ws
     cuts = [round(n * j / args.batches) for j in range(args.batches + 1)]
     batches = []
@@ -590,19 +591,21 @@ def append_bench(args):
         a, b = int(rp[lo]), int(rp[hi])
         batches.append((lo, (rp[lo:hi + 1] - a).contiguous(), ci[a:b]))
     bws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=max(hi - lo for lo, hi in zip(cuts, cuts[1:])))
-    c2, i2 = flash.alloc_index(p)
+    index2 = flash.alloc_index(p)
+    c2, i2 = flash.index_parts(p, index2)
 
     def grow():
         c2.zero_()
         for lo, brp, bci in batches:
-            flash.flash_build_index_append(p, brp, bci, lo, c2, i2, bws, stream=stream)
+            flash.flash_build_index_append(p, brp, bci, lo, index2, bws, stream=stream)
 
     grown = timed(grow, args.warmup + args.steps)
     L, M, R = p.L, p.M, p.R
+    c1, i1 = flash.index_parts(p, index1)
     same_counts = bool(torch.equal(c1, c2))
-    occ = torch.clamp(c1.view(L, M).long(), max=R)
+    occ = torch.clamp(c1.reshape(L, M).long(), max=R)
     mask = torch.arange(R, device="cuda")[None, None, :] < occ[:, :, None]
-    same_ids = bool(torch.equal(i1.view(L, M, R)[mask], i2.view(L, M, R)[mask]))
+    same_ids = bool(torch.equal(i1.reshape(L, M, R)[mask], i2.reshape(L, M, R)[mask]))
     t_one = float(np.median(one[args.warmup:]))
     t_grow = float(np.median(grown[args.warmup:]))
     out = {
@@ -646,9 +649,9 @@ def rerank_bench(args):
         spec = datagen.scaled(spec, args.rows)
     rp, ci = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
-    flash.flash_build_index(p, rp, ci, counts, ids, ws)
+    flash.flash_build_index(p, rp, ci, index, ws)
     del ws
     nq = min(args.queries, 100_000)
     qrp, qci = datagen.make_rows(dataclasses.replace(spec, n_rows=nq), 1, device="cuda", row_seed=2)
@@ -671,7 +674,7 @@ def rerank_bench(args):
             out.append(e0.elapsed_time(e1))
         return out
 
-    q_ms = timed(lambda: flash.flash_query_batch(p, counts, ids, spec.n_rows, qrp, qci, kc, cand, cc, qws,
+    q_ms = timed(lambda: flash.flash_query_batch(p, index, spec.n_rows, qrp, qci, kc, cand, cc, qws,
                                                  stream=stream), args.warmup + args.steps)
     c2 = cand.view(nq, kc)
     r_ms = timed(lambda: flash.flash_rerank_exact(flash.SIM_COSINE, rp, ci, qrp, qci, c2, k, oi, on,
@@ -754,14 +757,14 @@ def share_bench(args):
     rows = []
     for permille in (1000, 500, 200, 100, 50):
         p = flash.flash_params.make(5, 32, 3, 64, seed=1, share_permille=permille)
-        counts, ids = flash.alloc_index(p)
+        index = flash.alloc_index(p)
         ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
-        t_build = timed(lambda: flash.flash_build_index(p, rp, ci, counts, ids, ws, stream=stream), 3)
+        t_build = timed(lambda: flash.flash_build_index(p, rp, ci, index, ws, stream=stream), 3)
         del ws
         oi = torch.empty(nq * k, dtype=torch.int32, device="cuda")
         oc = torch.empty_like(oi)
         qws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=nq, k=k)
-        t_query = timed(lambda: flash.flash_query_batch(p, counts, ids, spec.n_rows, qrp, qci, k, oi, oc, qws,
+        t_query = timed(lambda: flash.flash_query_batch(p, index, spec.n_rows, qrp, qci, k, oi, oc, qws,
                                                         stream=stream), 3)
         ri = torch.empty_like(oi)
         rn = torch.empty_like(oi)
@@ -772,13 +775,14 @@ def share_bench(args):
         sz = torch.where(valid, rowlen[idv.clamp(min=0)], torch.ones(1, device="cuda", dtype=torch.float64))
         cos = torch.where(valid & (rn.view(nq, k) > 0), rn.view(nq, k).double() / torch.sqrt(qlen[:, None] * sz),
                           torch.zeros(1, device="cuda", dtype=torch.float64))
-        row = {"F": permille / 1000, "reservoirs": int(counts.numel()),
-               "index_bytes": int(counts.numel() * 4 + ids.numel() * 4),
+        n_res, _, words = flash.flash_index_layout(p)
+        row = {"F": permille / 1000, "reservoirs": int(n_res),
+               "index_bytes": int(words * 4),
                "build_ms": round(t_build, 3), "query_ms": round(t_query, 3),
                "S_at_10": round(float(cos.sum(dim=1).div(k).mean().item()), 4)}
         log(json.dumps(row))
         rows.append(row)
-        del counts, ids, qws
+        del index, qws
         torch.cuda.empty_cache()
     base = rows[0]
     out = {

@@ -28,13 +28,21 @@
  *    clamped to [0, nnz] on the device, so a malformed row_ptr cannot read
  *    outside col_idx (such a row is hashed as whatever lies in its clamped
  *    range, possibly empty).
- *  - Index layout (Sec. 3.5: memory O(L * R * Range)): counts uint32[L][M]
- *    and ids int32[L][M][R] with M = 2^(K * bits_per_hash).  counts[t][m] is
- *    the number of rows whose key in table t is m; slots
- *    [0, min(counts[t][m], R)) of ids[t][m] hold the kept row ids in
- *    ascending reservoir priority; later slots are not part of the index and
- *    are never read.  With shared reservoirs (flash_params.share_permille)
- *    the arrays are counts uint32[P] and ids int32[P][R] over the pool.
+ *  - Index layout (Sec. 3.5: memory O(L * R * Range)): one device array
+ *    `index`, int32[P][S], 16-byte aligned, holding the P = L * M reservoirs
+ *    (M = 2^(K * bits_per_hash); reservoir t * M + m is bucket m of table t)
+ *    S words apart, S = R + 4 rounded up to a multiple of 32 (128 bytes;
+ *    flash_index_layout gives P and S).  Word 0 of a reservoir is its
+ *    header: the number of rows whose key in table t is m (an unsigned
+ *    32-bit count stored in the int32 word).  Words 1..3 are reserved and
+ *    never read.  Words 4 .. 4 + min(count, R) - 1 hold the kept row ids in
+ *    ascending reservoir priority; later words are not part of the index
+ *    and hold anything.  The header and the first 28 slots share one
+ *    128-byte line, so a query's visit to a small bucket reads one line.
+ *    With shared reservoirs (flash_params.share_permille) P is the pool.
+ *    Every call that takes `index` refuses a pointer that is not 16-byte
+ *    aligned (FLASH_EINVAL).  FLASH_INDEX_LAYOUT names this layout; layout
+ *    1 (separate counts uint32[P] and ids int32[P][R] arrays) is gone.
  */
 #ifndef FLASH_H
 #define FLASH_H
@@ -57,6 +65,9 @@ extern "C" {
 #define FLASH_ENOSPC (-2)   /* workspace (or an output) too small */
 #define FLASH_EHIP (-3)     /* HIP runtime / launch error */
 #define FLASH_ENOTIMPL (-4) /* parameters outside what the kernels support */
+
+/* Version of the index layout described above. */
+#define FLASH_INDEX_LAYOUT 2
 
 /* Key of an empty row or query in every table (never inserted). */
 #define FLASH_EMPTY_KEY 0xFFFFFFFFu
@@ -100,10 +111,11 @@ typedef struct flash_params {
  * FLASH_ENOTIMPL with a message in flash_last_error(). */
 FLASH_API int flash_check_params(const flash_params *p);
 
-/* Host only.  Element counts of the two index arrays: counts (P) and ids
- * (P * R), P = L * M without reservoir sharing. */
-FLASH_API int flash_index_elems(const flash_params *p, uint64_t *counts_elems,
-                                uint64_t *ids_elems);
+/* Host only.  Shape of the index array: *reservoirs = P (L * M without
+ * reservoir sharing), *stride_words = S (words per reservoir) and
+ * *words = P * S, its length in int32 elements.  Any output may be NULL. */
+FLASH_API int flash_index_layout(const flash_params *p, uint64_t *reservoirs, uint32_t *stride_words,
+                                 uint64_t *words);
 
 /* Host only.  Workspace bytes needed by operation `op` for n_rows indexed rows
  * (insert/build/graph) or n_queries queries (query ops) and k results per
@@ -120,12 +132,12 @@ FLASH_API int flash_hash(const flash_params *p, int64_t n_rows, int64_t nnz,
                          uint32_t *codes, void *stream);
 
 /* Alg. 2 (adding phase) with Alg. 1's reservoir read as bottom-R priority
- * sampling.  Clears counts, then adds row i (id i, 0 <= i < n_rows) to bucket
+ * sampling.  Clears the index, then adds row i (id i, 0 <= i < n_rows) to bucket
  * keys[i][t] of every table t.  Keys that are FLASH_EMPTY_KEY or >= M are
  * skipped.  Requires n_rows * L < 2^32 and n_rows < 2^31.  The tables are
  * bit-identical for any launch order or configuration. */
 FLASH_API int flash_insert_keys(const flash_params *p, int64_t n_rows, const uint32_t *keys,
-                                uint32_t *counts, int32_t *ids, void *workspace,
+                                int32_t *index, void *workspace,
                                 size_t workspace_bytes, void *stream);
 
 /* Alg. 2 (adding phase) from CSR: flash_hash, then flash_insert_keys.  The keys are
@@ -133,16 +145,16 @@ FLASH_API int flash_insert_keys(const flash_params *p, int64_t n_rows, const uin
  * workspace. */
 FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t nnz,
                                 const int64_t *row_ptr, const int32_t *col_idx,
-                                uint32_t *counts, int32_t *ids, uint32_t *keys_out,
+                                int32_t *index, uint32_t *keys_out,
                                 void *workspace, size_t workspace_bytes, void *stream);
 
 /* Incremental insertion into a resident index (Sec. 3.2 item 2; Sec. 3.4:
  * rows are added independently).  Adds n_rows rows, given by their keys
  * (device uint32[n_rows][L], as flash_hash writes them), with ids id_base ..
- * id_base + n_rows - 1 to the index in counts/ids, which already holds rows
- * with other ids (a fresh index: counts all zero).  A reservoir keeps the R
+ * id_base + n_rows - 1 to `index`, which already holds rows with other ids
+ * (a fresh index: every header zero).  A reservoir keeps the R
  * lowest priorities of its arrivals, so after any sequence of calls the
- * index is bit-identical (counts and occupied slots) to one
+ * index is bit-identical (headers and occupied slots) to one
  * flash_insert_keys over all rows added, whatever the batching and order.
  * Ids must not repeat across calls (not checked).  0 <= id_base and
  * id_base + n_rows <= 2^32 / 2^ceil(log2(L+2)) (the largest index the
@@ -150,14 +162,14 @@ FLASH_API int flash_build_index(const flash_params *p, int64_t n_rows, int64_t n
  * FLASH_OP_INSERT for n_rows.  Calls on one index must be ordered on one
  * stream; n_rows = 0 enqueues nothing. */
 FLASH_API int flash_insert_keys_append(const flash_params *p, int64_t n_rows, const uint32_t *keys,
-                                       int64_t id_base, uint32_t *counts, int32_t *ids,
+                                       int64_t id_base, int32_t *index,
                                        void *workspace, size_t workspace_bytes, void *stream);
 
 /* flash_insert_keys_append from CSR rows: flash_hash into the workspace, then
  * the append.  Workspace: FLASH_OP_BUILD for n_rows. */
 FLASH_API int flash_build_index_append(const flash_params *p, int64_t n_rows, int64_t nnz,
                                        const int64_t *row_ptr, const int32_t *col_idx,
-                                       int64_t id_base, uint32_t *counts, int32_t *ids,
+                                       int64_t id_base, int32_t *index,
                                        void *workspace, size_t workspace_bytes, void *stream);
 
 /* Alg. 3 (querying phase) from precomputed keys qkeys uint32[n_queries][L].
@@ -170,7 +182,7 @@ FLASH_API int flash_build_index_append(const flash_params *p, int64_t n_rows, in
  * counts share one 32-bit word in the query's table).  Every id stored in
  * the index must be < n_indexed (not checked: a larger id may be dropped or
  * corrupted in the lists). */
-FLASH_API int flash_query_keys(const flash_params *p, const uint32_t *counts, const int32_t *ids,
+FLASH_API int flash_query_keys(const flash_params *p, const int32_t *index,
                                int64_t n_indexed, int64_t n_queries, const uint32_t *qkeys,
                                const int32_t *self_ids, int32_t k, int32_t *out_ids,
                                int32_t *out_counts, void *workspace, size_t workspace_bytes,
@@ -178,7 +190,7 @@ FLASH_API int flash_query_keys(const flash_params *p, const uint32_t *counts, co
 
 /* Alg. 3 (querying phase) from CSR queries: flash_hash of the queries into the
  * workspace, then flash_query_keys. */
-FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, const int32_t *ids,
+FLASH_API int flash_query_batch(const flash_params *p, const int32_t *index,
                                 int64_t n_indexed, int64_t n_queries, int64_t nnz,
                                 const int64_t *q_row_ptr, const int32_t *q_col_idx,
                                 const int32_t *self_ids, int32_t k, int32_t *out_ids,
@@ -197,8 +209,8 @@ FLASH_API int flash_query_batch(const flash_params *p, const uint32_t *counts, c
  * shares that device's area: calls that overlap on one device (other
  * streams, other threads) race and give wrong results, so order them on one
  * stream.  The area's first use on a device looks its address up once. */
-FLASH_API int flash_query_batch_noalloc(const flash_params *p, const uint32_t *counts,
-                                        const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+FLASH_API int flash_query_batch_noalloc(const flash_params *p, const int32_t *index,
+                                        int64_t n_indexed, int64_t n_queries,
                                         int64_t nnz, const int64_t *q_row_ptr,
                                         const int32_t *q_col_idx, const int32_t *self_ids, int32_t k,
                                         int32_t *out_ids, int32_t *out_counts, void *stream);
@@ -211,8 +223,8 @@ FLASH_API size_t flash_noalloc_scratch_bytes(void);
  * k_per_query[q] ids (device int32[n_queries]; values are clamped to
  * [1, k_max]) and its output row, of stride k_max, is padded with (-1, 0)
  * after them.  1 <= k_max <= 1024.  Workspace: FLASH_OP_QUERY_KEYS. */
-FLASH_API int flash_query_keys_mixed(const flash_params *p, const uint32_t *counts,
-                                     const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+FLASH_API int flash_query_keys_mixed(const flash_params *p, const int32_t *index,
+                                     int64_t n_indexed, int64_t n_queries,
                                      const uint32_t *qkeys, const int32_t *self_ids,
                                      const int32_t *k_per_query, int32_t k_max, int32_t *out_ids,
                                      int32_t *out_counts, void *workspace, size_t workspace_bytes,
@@ -221,8 +233,8 @@ FLASH_API int flash_query_keys_mixed(const flash_params *p, const uint32_t *coun
 /* flash_query_batch with a k per query: CSR queries are hashed into the
  * workspace, then answered as flash_query_keys_mixed.  Workspace:
  * FLASH_OP_QUERY. */
-FLASH_API int flash_query_batch_mixed(const flash_params *p, const uint32_t *counts,
-                                      const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+FLASH_API int flash_query_batch_mixed(const flash_params *p, const int32_t *index,
+                                      int64_t n_indexed, int64_t n_queries,
                                       int64_t nnz, const int64_t *q_row_ptr,
                                       const int32_t *q_col_idx, const int32_t *self_ids,
                                       const int32_t *k_per_query, int32_t k_max, int32_t *out_ids,
@@ -230,11 +242,11 @@ FLASH_API int flash_query_batch_mixed(const flash_params *p, const uint32_t *cou
                                       void *stream);
 
 /* Sec. 1 / Sec. 4.3: approximate k-NN graph.  Builds the index of all rows
- * into counts/ids, then queries every row with its own keys, leaving the row
+ * into `index`, then queries every row with its own keys, leaving the row
  * itself out. */
 FLASH_API int flash_knn_graph(const flash_params *p, int64_t n_rows, int64_t nnz,
                               const int64_t *row_ptr, const int32_t *col_idx, int32_t k,
-                              uint32_t *counts, int32_t *ids, int32_t *out_ids,
+                              int32_t *index, int32_t *out_ids,
                               int32_t *out_counts, void *workspace, size_t workspace_bytes,
                               void *stream);
 
@@ -309,8 +321,8 @@ FLASH_API int flash_set_tuning(const flash_tuning *t);
  * The outputs hold the batch's result (the same for every candidate).
  * Arguments as flash_query_batch_mixed; workspace FLASH_OP_QUERY.  On error
  * the previous tuning is restored. */
-FLASH_API int flash_autotune_query_batch(const flash_params *p, const uint32_t *counts,
-                                         const int32_t *ids, int64_t n_indexed, int64_t n_queries,
+FLASH_API int flash_autotune_query_batch(const flash_params *p, const int32_t *index,
+                                         int64_t n_indexed, int64_t n_queries,
                                          int64_t nnz, const int64_t *q_row_ptr,
                                          const int32_t *q_col_idx, const int32_t *self_ids,
                                          const int32_t *k_per_query, int32_t k_max,

@@ -29,8 +29,7 @@ namespace flashk {
 namespace {
 
 struct QueryArgs {
-  const uint32_t* counts;
-  const int32_t* ids;
+  const int32_t* index;       // reservoir b: count at index[b * S], slot i at index[b * S + kSlot0 + i]
   const uint32_t* qkeys;
   const int32_t* self_ids;
   int32_t* out_ids;
@@ -44,7 +43,8 @@ struct QueryArgs {
   uint32_t M;
   int L, R, k, self_mode, cbits;   // k: the row stride of the outputs (the largest k)
   const int32_t* k_per_query;       // per-query k (clamped to [1, k]) if not null
-  int r_aligned;              // R % 4 == 0: a task is one 16-byte load
+  uint32_t S;                 // words per reservoir (a multiple of 32, so every task is one
+                              // aligned 16-byte load)
   uint32_t max_total;         // candidates this launch's table accepts
   uint32_t sb;                // survivor buffer entries
   int shared;                 // reservoirs shared through the seeded map
@@ -294,7 +294,7 @@ __device__ __forceinline__ void count_ids16(uint32_t* tab, const uint32_t (&idv)
   }
 }
 
-template <int CAP, int LCH, bool ALIGNED>
+template <int CAP, int LCH>
 __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
   constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
   constexpr int W = kWave * U;         // tasks per window
@@ -341,9 +341,9 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
         const uint32_t key = a.qkeys[q * (uint64_t)L + t];
         if (key < a.M) {
           const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, key);
-          const uint32_t cnt = a.counts[bucket];
+          const uint32_t cnt = (uint32_t)a.index[bucket * a.S];
           nt = cnt < R ? cnt : R;
-          base = bucket * R;
+          base = bucket * a.S + kSlot0;
         }
       }
       const uint32_t ct = (nt + 3) >> 2;
@@ -400,15 +400,7 @@ __global__ __launch_bounds__(64) void count_topk_kernel(QueryArgs a) {
         const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
         const uint32_t room = ti.z - 4u * tc;  // occupied slots of this bucket from here, >= 1
         vmask[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
-        if (ALIGNED) {
-          ids4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
-        } else {
-          const uint32_t last = room - 1;
-          ids4[u].x = (uint32_t)a.ids[addr];
-          ids4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
-          ids4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
-          ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
-        }
+        ids4[u] = *reinterpret_cast<const uint4*>(a.index + addr);
       }
       uint32_t idv[16];
       uint32_t valid = 0;
@@ -579,7 +571,7 @@ __host__ __device__ inline size_t block_smem_bytes(int cap, int L, uint32_t sb, 
 // turn; the table is swept in place (no compaction) with the sweeps split
 // over all threads; block-wide sums go through LDS words.  Wave 0 sorts and
 // writes the survivors.
-template <int CAP, int LCH, bool ALIGNED, int NW>
+template <int CAP, int LCH, int NW>
 __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) {
   constexpr int U = 4;                 // tasks (of 4 candidates) per lane per window
   constexpr int W = kWave * U;         // tasks per window
@@ -624,9 +616,9 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
         const uint32_t key = a.qkeys[q * (uint64_t)L + t];
         if (key < a.M) {
           const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, key);
-          const uint32_t cnt = a.counts[bucket];
+          const uint32_t cnt = (uint32_t)a.index[bucket * a.S];
           nt = cnt < R ? cnt : R;
-          base = bucket * R;
+          base = bucket * a.S + kSlot0;
         }
       }
       const uint32_t ct = (nt + 3) >> 2;
@@ -676,15 +668,7 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
         const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
         const uint32_t room = ti.z - 4u * tc;
         vmask[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
-        if (ALIGNED) {
-          ids4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
-        } else {
-          const uint32_t last = room - 1;
-          ids4[u].x = (uint32_t)a.ids[addr];
-          ids4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
-          ids4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
-          ids4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
-        }
+        ids4[u] = *reinterpret_cast<const uint4*>(a.index + addr);
       }
       uint32_t idv[16];
       uint32_t valid = 0;
@@ -897,9 +881,13 @@ __host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
   return kBmWords + 4u * (uint32_t)L + (uint32_t)kNB + kCut + (kmax <= kSmallK ? 0u : 2 * k4);
 }
 
-__device__ __forceinline__ uint32_t filter_bit(uint32_t id) { return (id * 0x9E3779B1u) >> 17; }
-__device__ __forceinline__ uint32_t ts_slot(uint32_t id) { return (id * 0x85EBCA77u) >> 24; }
-__device__ __forceinline__ uint32_t b2_bit(uint32_t id) { return (id * 0xC2B2AE35u) >> 19; }
+// One multiplicative hash per id serves all three structures: the filter
+// bit is its top 15 bits (word = top 10), the suspect table slot its top 8,
+// and the suspects' filter bit its top 13 (word = the slot, so one address
+// reaches both).  An id that shares a suspect's top bits costs at most a
+// longer probe; results never depend on the hash.
+__device__ __forceinline__ uint32_t id_hash(uint32_t id) { return id * 0x9E3779B1u; }
+__device__ __forceinline__ uint32_t ts_slot_of(uint32_t h) { return h >> 24; }
 
 // Bins [0, 512): lane l holds bins 8l .. 8l+7.  Returns the bin b* where the
 // running count first reaches `need` (1 <= need <= total), with *before =
@@ -953,7 +941,7 @@ __device__ __forceinline__ uint32_t find_cut_bin(uint32_t* bins, uint32_t need, 
 
 __device__ __forceinline__ uint32_t bitlen64(uint64_t x) { return x ? 64u - (uint32_t)__clzll((long long)x) : 0u; }
 
-template <int LCH, bool ALIGNED>
+template <int LCH>
 // At most 96 VGPRs (five waves per SIMD): the stage waits on memory, and
 // 20 waves per CU keep more loads in flight than 16 with fewer spills.
 __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
@@ -990,9 +978,12 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
 
   uint32_t ovf_buf = 0, ovf_n = 0;
   const uint64_t nq = a.qlist ? (uint64_t)*a.qlist_len : (uint64_t)a.n_queries;
-  // the next query's keys and bucket counts are loaded while the current one
-  // is processed: key[c] / cnt[c] of lane t = table c * 64 + t
-  uint32_t pkey[LCH], pcnt[LCH];
+  // the next query's keys are loaded while the current one is processed:
+  // key[c] of lane t = table c * 64 + t.  The bucket counts are read when the
+  // query starts: a count loaded a query ahead brings in the reservoir's first
+  // line (the header shares it with the first slots), which the L2 has mostly
+  // evicted again by the time the gather reads the slots.
+  uint32_t pkey[LCH];
   auto load_keys = [&](uint64_t wq) {
     const uint64_t qq = wq < nq ? (a.qlist ? (uint64_t)a.qlist[wq] : wq) : 0;
 #pragma unroll
@@ -1001,15 +992,7 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
       pkey[c] = (wq < nq && t < L) ? a.qkeys[qq * (uint64_t)L + t] : kEmpty;
     }
   };
-  auto load_counts = [&]() {
-#pragma unroll
-    for (int c = 0; c < LCH; ++c) {
-      const uint32_t t = (uint32_t)c * 64 + lane;
-      pcnt[c] = pkey[c] < a.M ? a.counts[reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, pkey[c])] : 0u;
-    }
-  };
   load_keys(blockIdx.x);
-  load_counts();
   for (uint64_t w = blockIdx.x; w < nq; w += gridDim.x) {
     const uint64_t q = a.qlist ? (uint64_t)a.qlist[w] : w;
     const int64_t self = a.self_mode == 1 ? (int64_t)a.self_ids[q] : (a.self_mode == 2 ? (int64_t)q : -1);
@@ -1025,8 +1008,9 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
       uint64_t base = 0;
       if (pkey[c] < a.M) {
         const uint64_t bucket = reservoir_of(a.shared != 0, a.s_r, a.P, a.M, t, pkey[c]);
-        nt = pcnt[c] < R ? pcnt[c] : R;
-        base = bucket * R;
+        const uint32_t cnt = (uint32_t)a.index[bucket * a.S];
+        nt = cnt < R ? cnt : R;
+        base = bucket * a.S + kSlot0;
       }
       const uint32_t ct = (nt + 3) >> 2;
       const uint32_t packed = (nt << 16) | ct;
@@ -1073,10 +1057,10 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
       // every task's 16-byte load is issued before any is used
       uint32_t tcarry = 0;
       uint4 v4[U];
-      uint32_t vm[U];
+      uint32_t room[U];   // occupied slots of the task's bucket from its first (0: no task)
 #pragma unroll
       for (int u = 0; u < U; ++u) {
-        vm[u] = 0;
+        room[u] = 0;
         v4[u] = make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
         if ((uint32_t)u * kWave < n_tasks) {
           const uint32_t mk = marks[u * kWave + lane];
@@ -1088,53 +1072,53 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
           const uint32_t tc = task < n_tasks ? task : n_tasks - 1;
           const uint4 ti = tinfo[tt - 1];
           const uint64_t addr = (((uint64_t)ti.y << 32) | ti.x) + 4ull * tc;
-          const uint32_t room = ti.z - 4u * tc;
-          vm[u] = task < n_tasks ? (room >= 4 ? 0xFu : ((1u << room) - 1u)) : 0u;
-          if (ALIGNED) {
-            v4[u] = *reinterpret_cast<const uint4*>(a.ids + addr);
-          } else {
-            const uint32_t last = room - 1;
-            v4[u].x = (uint32_t)a.ids[addr];
-            v4[u].y = (uint32_t)a.ids[addr + (last < 1 ? last : 1)];
-            v4[u].z = (uint32_t)a.ids[addr + (last < 2 ? last : 2)];
-            v4[u].w = (uint32_t)a.ids[addr + (last < 3 ? last : 3)];
-          }
+          room[u] = task < n_tasks ? ti.z - 4u * tc : 0u;
+          v4[u] = *reinterpret_cast<const uint4*>(a.index + addr);
         }
       }
+      // the query's own id (never a real id when absent: kEmpty is no candidate)
+      const uint32_t self32 = self >= 0 ? (uint32_t)self : kEmpty;
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         const uint32_t vv[4] = {v4[u].x, v4[u].y, v4[u].z, v4[u].w};
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
-          idv[4 * u + i] = (((vm[u] >> i) & 1u) && (int64_t)vv[i] != self) ? vv[i] : kEmpty;
+        for (int i = 0; i < 4; ++i) idv[4 * u + i] = (room[u] > (uint32_t)i && vv[i] != self32) ? vv[i] : kEmpty;
       }
-      load_counts();
-      // 3a. filter: a candidate whose bit is already set is a suspect
+      // 3a. filter: a candidate whose bit is already set is a suspect.  The
+      // four atomics of a task are all issued before any result is used, so
+      // they are waited for once (absent candidates take no part: a shared
+      // word would serialise them).
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if ((uint32_t)u * kWave < n_tasks) {
-          uint32_t seen[4];
+          uint32_t bit[4], old[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const uint32_t x = idv[4 * u + i];
-            const uint32_t b = filter_bit(x);
-            const uint32_t bit = 1u << (b & 31u);
-            seen[i] = x != kEmpty ? (atomicOr(&bm[b >> 5], bit) & bit) : 0u;
+            const uint32_t h = id_hash(x);
+            bit[i] = 1u << ((h >> 17) & 31u);
+            old[i] = 0;
+            if (x != kEmpty) old[i] = atomicOr(&bm[h >> 22], bit[i]);
           }
+          uint32_t seen[4];
+          uint64_t m[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const uint64_t m = __ballot(seen[i] != 0);
-            if (m) {
-              const uint32_t p = nsus + mbcnt(m);
+            seen[i] = old[i] & bit[i];
+            m[i] = __ballot(seen[i] != 0);
+          }
+          if (m[0] | m[1] | m[2] | m[3]) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t p = nsus + mbcnt(m[i]);
               if (seen[i] && p < kSusp) susp[p] = idv[4 * u + i];
-              nsus += (uint32_t)__popcll(m);
+              nsus += (uint32_t)__popcll(m[i]);
             }
           }
         }
       }
       hand_on = nsus > kSusp;
     }
-    if (!touched) load_counts();
     uint32_t nmulti = 0, nsing = 0;
     if (!hand_on) {
       if (nsus) {
@@ -1148,9 +1132,9 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
       // most half full), and their bits into the suspects' filter
       for (uint32_t i = lane; i < nsus; i += kWave) {
         const uint32_t x = susp[i];
-        const uint32_t h2 = b2_bit(x);
-        atomicOr(&b2[h2 >> 5], 1u << (h2 & 31u));
-        uint32_t sl = ts_slot(x);
+        const uint32_t h = id_hash(x);
+        uint32_t sl = ts_slot_of(h);
+        atomicOr(&b2[sl], 1u << ((h >> 19) & 31u));
         for (;;) {
           const uint32_t o = atomicCAS(&tsk[sl], kEmpty, x);
           if (o == kEmpty || o == x) break;
@@ -1166,21 +1150,22 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
 #pragma unroll
       for (int u = 0; u < U; ++u) {
         if ((uint32_t)u * kWave < n_tasks) {
-          uint32_t sl[4], o[4], f2[4];
+          // the suspects' filter word and the table slot of every candidate,
+          // read together (unused when the query has no suspects)
+          uint32_t sl[4], w2[4], o[4];
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
-            const uint32_t h2 = b2_bit(idv[4 * u + i]);
-            f2[i] = (nsus && idv[4 * u + i] != kEmpty) ? (b2[h2 >> 5] >> (h2 & 31u)) & 1u : 0u;
-          }
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            sl[i] = ts_slot(idv[4 * u + i]);
-            o[i] = f2[i] ? tsk[sl[i]] : kEmpty;
+            const uint32_t h = id_hash(idv[4 * u + i]);
+            sl[i] = ts_slot_of(h);
+            w2[i] = __builtin_amdgcn_ubfe(b2[sl[i]], h >> 19, 1u);   // bit (h >> 19) mod 32
+            o[i] = tsk[sl[i]];
           }
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const uint32_t x = idv[4 * u + i];
-            uint32_t s2 = sl[i], o2 = o[i];
+            // (an absent candidate may pass: it then finds no equal entry)
+            const bool f2 = nsus && w2[i] != 0;
+            uint32_t s2 = sl[i], o2 = f2 ? o[i] : kEmpty;
             if (o2 != x && o2 != kEmpty) {   // another id holds the slot: walk on
               do {
                 s2 = (s2 + 1) & (kTs - 1);
@@ -1235,34 +1220,58 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
         // The bins below b* now hold the start of their groups; scattering
         // advances each to the group's end.
         uint32_t ncut = 0;
-        auto place = [&](uint32_t y) {
-          const uint32_t b = y < wid0 ? y >> s0 : (uint32_t)(kNB - 1);
-          const bool lowbin = y != kEmpty && b < bstar;
-          const bool inbin = y != kEmpty && b == bstar;
-          if (lowbin) grp[atomicAdd(&bins[b], 1u)] = y;
-          const uint64_t mp = __ballot(inbin);
-          if (mp) {
-            if (inbin && ncut + mbcnt(mp) < kCut) cutb[ncut + mbcnt(mp)] = y;
-            ncut += (uint32_t)__popcll(mp);
+        // four ids per lane at a time: their cursor atomics are all issued
+        // before any result is used.  An absent id (kEmpty) falls in the
+        // last bin, which is above b*.
+        auto place4 = [&](const uint32_t (&y)[4]) {
+          uint32_t b[4], pos[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            b[i] = y[i] < wid0 ? y[i] >> s0 : (uint32_t)(kNB - 1);
+            pos[i] = 0;
+            if (b[i] < bstar) pos[i] = atomicAdd(&bins[b[i]], 1u);
+          }
+          uint64_t mp[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            if (b[i] < bstar) grp[pos[i]] = y[i];
+            mp[i] = __ballot(b[i] == bstar);
+          }
+          if (mp[0] | mp[1] | mp[2] | mp[3]) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const uint32_t p = ncut + mbcnt(mp[i]);
+              if (b[i] == bstar && p < kCut) cutb[p] = y[i];
+              ncut += (uint32_t)__popcll(mp[i]);
+            }
           }
         };
 #pragma unroll
         for (int u = 0; u < U; ++u)
           if ((uint32_t)u * kWave < n_tasks) {
-#pragma unroll
-            for (int i = 0; i < 4; ++i) place(idv[4 * u + i]);
+            const uint32_t y4[4] = {idv[4 * u], idv[4 * u + 1], idv[4 * u + 2], idv[4 * u + 3]};
+            place4(y4);
           }
         uint32_t nmc = 0;
         if (nsus) {
-          for (uint32_t i0 = 0; i0 < kTs; i0 += kWave) {
-            const uint32_t x = tsk[i0 + lane];
-            const uint32_t c = x != kEmpty ? tsc[i0 + lane] : 0u;
-            place(c == 1 ? x : kEmpty);
-            // ids of count >= 2: key (L - count, id)
-            const bool mult = c >= 2;
-            const uint64_t mm = __ballot(mult);
-            if (mult) surv[nmc + mbcnt(mm)] = ((L - c) << idshift) | x;
-            nmc += (uint32_t)__popcll(mm);
+          for (uint32_t i0 = 0; i0 < kTs; i0 += 4 * kWave) {
+            uint32_t x4[4], c4[4], y4[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              x4[j] = tsk[i0 + j * kWave + lane];
+              c4[j] = x4[j] != kEmpty ? tsc[i0 + j * kWave + lane] : 0u;
+              y4[j] = c4[j] == 1 ? x4[j] : kEmpty;
+            }
+            place4(y4);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const uint32_t x = x4[j], c = c4[j];
+              // ids of count >= 2: key (L - count, id)
+              const bool mult = c >= 2;
+              const uint64_t mm = __ballot(mult);
+              if (mult) surv[nmc + mbcnt(mm)] = ((L - c) << idshift) | x;
+              nmc += (uint32_t)__popcll(mm);
+            }
           }
         }
         wave_lds_sync();
@@ -1433,38 +1442,33 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
   if (ovf_n) flush_overflow(a, ovf_buf, ovf_n);
 }
 
-template <int LCH, bool ALIGNED>
+template <int LCH>
 hipError_t launch_fast(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = 4 * (size_t)fast_lds_words(a.L, (uint32_t)a.k);
-  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_fast_kernel<LCH, ALIGNED>), lds);
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_fast_kernel<LCH>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((count_topk_fast_kernel<LCH, ALIGNED>), dim3(grid), dim3(64), lds, st, a);
+  hipLaunchKernelGGL((count_topk_fast_kernel<LCH>), dim3(grid), dim3(64), lds, st, a);
   return hipGetLastError();
 }
 
-hipError_t launch_fast_any(const QueryArgs& a, bool aligned, int grid, hipStream_t st) {
+hipError_t launch_fast_any(const QueryArgs& a, int grid, hipStream_t st) {
   switch ((a.L + 63) / 64) {
-    case 1: return aligned ? launch_fast<1, true>(a, grid, st) : launch_fast<1, false>(a, grid, st);
-    case 2: return aligned ? launch_fast<2, true>(a, grid, st) : launch_fast<2, false>(a, grid, st);
-    case 3: return aligned ? launch_fast<3, true>(a, grid, st) : launch_fast<3, false>(a, grid, st);
-    case 4: return aligned ? launch_fast<4, true>(a, grid, st) : launch_fast<4, false>(a, grid, st);
+    case 1: return launch_fast<1>(a, grid, st);
+    case 2: return launch_fast<2>(a, grid, st);
+    case 3: return launch_fast<3>(a, grid, st);
+    case 4: return launch_fast<4>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int CAP, int LCH, bool ALIGNED>
-hipError_t launch_kernel(const QueryArgs& a, int grid, hipStream_t st) {
-  const size_t lds = smem_bytes(CAP, a.L, a.sb);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH, ALIGNED>), lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((count_topk_kernel<CAP, LCH, ALIGNED>), dim3(grid), dim3(64), lds, st, a);
-  return hipGetLastError();
-}
-
 template <int CAP, int LCH>
 hipError_t launch_cap(const QueryArgs& a, int grid, hipStream_t st) {
-  return a.r_aligned ? launch_kernel<CAP, LCH, true>(a, grid, st) : launch_kernel<CAP, LCH, false>(a, grid, st);
+  const size_t lds = smem_bytes(CAP, a.L, a.sb);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_kernel<CAP, LCH>), lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((count_topk_kernel<CAP, LCH>), dim3(grid), dim3(64), lds, st, a);
+  return hipGetLastError();
 }
 
 template <int LCH>
@@ -1489,27 +1493,21 @@ hipError_t launch_any(int cap, const QueryArgs& a, int grid, hipStream_t st) {
   }
 }
 
-template <int CAP, int LCH, bool ALIGNED, int NW>
+template <int CAP, int LCH, int NW>
 hipError_t launch_block_kernel(const QueryArgs& a, int grid, hipStream_t st) {
   const size_t lds = block_smem_bytes(CAP, a.L, a.sb, NW);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_block_kernel<CAP, LCH, ALIGNED, NW>), lds);
+  const hipError_t e = allow_lds(reinterpret_cast<const void*>(&count_topk_block_kernel<CAP, LCH, NW>), lds);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((count_topk_block_kernel<CAP, LCH, ALIGNED, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
+  hipLaunchKernelGGL((count_topk_block_kernel<CAP, LCH, NW>), dim3(grid), dim3(64 * NW), lds, st, a);
   return hipGetLastError();
-}
-
-template <int CAP, int LCH, int NW>
-hipError_t launch_block_aligned(const QueryArgs& a, int grid, hipStream_t st) {
-  return a.r_aligned ? launch_block_kernel<CAP, LCH, true, NW>(a, grid, st)
-                     : launch_block_kernel<CAP, LCH, false, NW>(a, grid, st);
 }
 
 template <int LCH, int NW>
 hipError_t launch_block_cap(int cap, const QueryArgs& a, int grid, hipStream_t st) {
   switch (cap) {
-    case 8192: return launch_block_aligned<8192, LCH, NW>(a, grid, st);
-    case 16384: return launch_block_aligned<16384, LCH, NW>(a, grid, st);
+    case 8192: return launch_block_kernel<8192, LCH, NW>(a, grid, st);
+    case 16384: return launch_block_kernel<16384, LCH, NW>(a, grid, st);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1559,14 +1557,14 @@ QueryWs query_ws_carve(const Cfg&, int64_t n_queries, void* ws) {
 
 // Query stages: each launch takes the queries whose candidate total fits its
 // table at <= 3/4 load (the last takes every query) and hands the rest on.
-hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
+hipError_t launch_query(const Cfg& c, const int32_t* index,
                         int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                         const int32_t* self_ids, int self_mode, int32_t k, const int32_t* k_per_query,
                         int32_t* out_ids, int32_t* out_counts, const QueryWs& w, hipStream_t st) {
   if (n_queries <= 0) return hipSuccess;
   QueryArgs a = {};
-  a.counts = counts;
-  a.ids = ids;
+  a.index = index;
+  a.S = c.S;
   a.qkeys = qkeys;
   a.self_ids = self_ids;
   a.out_ids = out_ids;
@@ -1583,7 +1581,6 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
   a.self_mode = self_mode;
   a.k_per_query = k_per_query;
   a.cbits = 32 - __builtin_clz((unsigned)c.L + 1u);
-  a.r_aligned = (c.R % 4) == 0 && (((uintptr_t)ids) & 15) == 0;
 
   const uint32_t full = (uint32_t)c.L * (uint32_t)c.R;  // most candidates a query can have
   uint32_t last = 1024;
@@ -1623,7 +1620,7 @@ hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids
     b.ovf_list = w.ovf_list[0];
     b.ovf_len = w.ovf_len;
     const int64_t want = (int64_t)cus * per_cu;
-    if ((e = launch_fast_any(b, a.r_aligned != 0, (int)(n_queries < want ? n_queries : want), st)) != hipSuccess) return e;
+    if ((e = launch_fast_any(b, (int)(n_queries < want ? n_queries : want), st)) != hipSuccess) return e;
   }
   for (int s = first; s < n_stage + first; ++s) {
     QueryArgs b = a;

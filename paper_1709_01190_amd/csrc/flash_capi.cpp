@@ -43,6 +43,7 @@ int make_cfg(const flash_params* p, Cfg* c) {
   c->L = p->L;
   c->b = p->bits_per_hash;
   c->R = p->R;
+  c->S = reservoir_words(p->R);
   c->B = p->K * p->L;
   c->A = p->densify_attempts;
   c->M = 1u << (p->K * p->bits_per_hash);
@@ -89,6 +90,12 @@ int check_query(const Cfg& c, int64_t n_indexed, int64_t n_queries, int32_t k) {
 }
 
 size_t keys_bytes(const Cfg& c, int64_t n) { return align256(4 * (uint64_t)n * (uint64_t)c.L); }
+
+int check_index(const int32_t* index) {
+  if (!index) return fail(FLASH_EINVAL, "index is NULL");
+  if (((uintptr_t)index & 15) != 0) return fail(FLASH_EINVAL, "index must be 16-byte aligned");
+  return FLASH_OK;
+}
 
 }  // namespace
 
@@ -204,12 +211,14 @@ FLASH_API int flash_check_params(const flash_params* p) {
   return make_cfg(p, &c);
 }
 
-FLASH_API int flash_index_elems(const flash_params* p, uint64_t* counts_elems, uint64_t* ids_elems) {
+FLASH_API int flash_index_layout(const flash_params* p, uint64_t* reservoirs, uint32_t* stride_words,
+                                 uint64_t* words) {
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
-  if (counts_elems) *counts_elems = c.P;
-  if (ids_elems) *ids_elems = c.P * (uint64_t)c.R;
+  if (reservoirs) *reservoirs = c.P;
+  if (stride_words) *stride_words = c.S;
+  if (words) *words = c.P * (uint64_t)c.S;
   return FLASH_OK;
 }
 
@@ -252,18 +261,19 @@ FLASH_API int flash_hash(const flash_params* p, int64_t n_rows, int64_t nnz, con
 }
 
 FLASH_API int flash_insert_keys(const flash_params* p, int64_t n_rows, const uint32_t* keys,
-                                uint32_t* counts, int32_t* ids, void* workspace,
+                                int32_t* index, void* workspace,
                                 size_t workspace_bytes, void* stream) {
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_rows(c, n_rows, true))) return r;
-  if (!counts || !ids || (n_rows > 0 && !keys)) return fail(FLASH_EINVAL, "NULL array");
+  if ((r = check_index(index))) return r;
+  if (n_rows > 0 && !keys) return fail(FLASH_EINVAL, "NULL array");
   const size_t need = insert_ws_bytes(c, n_rows);
   if (!workspace || workspace_bytes < need)
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_INSERT)");
   const InsertWs w = insert_ws_carve(c, n_rows, workspace);
-  hipError_t e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, w, (hipStream_t)stream);
+  hipError_t e = launch_insert(c, n_rows, keys, 0u, false, index, w, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
@@ -284,32 +294,33 @@ int check_append(const Cfg& c, int64_t n_rows, int64_t id_base) {
 }  // namespace
 
 FLASH_API int flash_insert_keys_append(const flash_params* p, int64_t n_rows, const uint32_t* keys,
-                                       int64_t id_base, uint32_t* counts, int32_t* ids, void* workspace,
+                                       int64_t id_base, int32_t* index, void* workspace,
                                        size_t workspace_bytes, void* stream) {
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_append(c, n_rows, id_base))) return r;
-  if (!counts || !ids || (n_rows > 0 && !keys)) return fail(FLASH_EINVAL, "NULL array");
+  if ((r = check_index(index))) return r;
+  if (n_rows > 0 && !keys) return fail(FLASH_EINVAL, "NULL array");
   const size_t need = insert_ws_bytes(c, n_rows);
   if (n_rows > 0 && (!workspace || workspace_bytes < need))
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_INSERT)");
   if (n_rows == 0) return FLASH_OK;
   const InsertWs w = insert_ws_carve(c, n_rows, workspace);
-  hipError_t e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, counts, ids, w, (hipStream_t)stream);
+  hipError_t e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, index, w, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
 FLASH_API int flash_build_index_append(const flash_params* p, int64_t n_rows, int64_t nnz,
                                        const int64_t* row_ptr, const int32_t* col_idx, int64_t id_base,
-                                       uint32_t* counts, int32_t* ids, void* workspace,
+                                       int32_t* index, void* workspace,
                                        size_t workspace_bytes, void* stream) {
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_append(c, n_rows, id_base))) return r;
   if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
-  if (!counts || !ids) return fail(FLASH_EINVAL, "NULL index array");
+  if ((r = check_index(index))) return r;
   const size_t kb = keys_bytes(c, n_rows);
   const size_t need = kb + insert_ws_bytes(c, n_rows);
   if (n_rows > 0 && (!workspace || workspace_bytes < need))
@@ -319,21 +330,21 @@ FLASH_API int flash_build_index_append(const flash_params* p, int64_t n_rows, in
   uint32_t* keys = (uint32_t*)workspace;
   hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, counts, ids, insert_ws_carve(c, n_rows, (char*)workspace + kb),
+  e = launch_insert(c, n_rows, keys, (uint32_t)id_base, true, index, insert_ws_carve(c, n_rows, (char*)workspace + kb),
                     s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
 FLASH_API int flash_build_index(const flash_params* p, int64_t n_rows, int64_t nnz,
-                                const int64_t* row_ptr, const int32_t* col_idx, uint32_t* counts,
-                                int32_t* ids, uint32_t* keys_out, void* workspace,
+                                const int64_t* row_ptr, const int32_t* col_idx, int32_t* index,
+                                uint32_t* keys_out, void* workspace,
                                 size_t workspace_bytes, void* stream) {
   Cfg c;
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_rows(c, n_rows, true))) return r;
   if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
-  if (!counts || !ids) return fail(FLASH_EINVAL, "NULL index array");
+  if ((r = check_index(index))) return r;
   const size_t kb = keys_bytes(c, n_rows);
   const size_t need = kb + insert_ws_bytes(c, n_rows);
   if (!workspace || workspace_bytes < need)
@@ -343,11 +354,11 @@ FLASH_API int flash_build_index(const flash_params* p, int64_t n_rows, int64_t n
   hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
   const InsertWs w = insert_ws_carve(c, n_rows, (char*)workspace + kb);
-  e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, w, s);
+  e = launch_insert(c, n_rows, keys, 0u, false, index, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "reservoir_insert");
 }
 
-FLASH_API int flash_query_keys(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_query_keys(const flash_params* p, const int32_t* index,
                                int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                                const int32_t* self_ids, int32_t k, int32_t* out_ids,
                                int32_t* out_counts, void* workspace, size_t workspace_bytes,
@@ -356,18 +367,19 @@ FLASH_API int flash_query_keys(const flash_params* p, const uint32_t* counts, co
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_query(c, n_indexed, n_queries, k))) return r;
-  if (n_queries > 0 && (!counts || !ids || !qkeys || !out_ids || !out_counts))
+  if (n_queries > 0 && (r = check_index(index))) return r;
+  if (n_queries > 0 && (!qkeys || !out_ids || !out_counts))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t need = query_ws_bytes(c, n_queries);
   if (!workspace || workspace_bytes < need)
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY_KEYS)");
   const QueryWs w = query_ws_carve(c, n_queries, workspace);
-  hipError_t e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
+  hipError_t e = launch_query(c, index, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
                               k, nullptr, out_ids, out_counts, w, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
-FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_query_batch(const flash_params* p, const int32_t* index,
                                 int64_t n_indexed, int64_t n_queries, int64_t nnz,
                                 const int64_t* q_row_ptr, const int32_t* q_col_idx,
                                 const int32_t* self_ids, int32_t k, int32_t* out_ids,
@@ -378,7 +390,8 @@ FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, c
   if (r) return r;
   if ((r = check_query(c, n_indexed, n_queries, k))) return r;
   if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
-  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts))
+  if (n_queries > 0 && (r = check_index(index))) return r;
+  if (n_queries > 0 && (!out_ids || !out_counts))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t kb = keys_bytes(c, n_queries);
   const size_t need = kb + query_ws_bytes(c, n_queries);
@@ -390,7 +403,7 @@ FLASH_API int flash_query_batch(const flash_params* p, const uint32_t* counts, c
   const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
   hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k,
+  e = launch_query(c, index, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k,
                    nullptr, out_ids, out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
@@ -440,7 +453,7 @@ extern "C" {
 
 FLASH_API size_t flash_noalloc_scratch_bytes(void) { return kNoAllocScratchBytes; }
 
-FLASH_API int flash_query_batch_noalloc(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_query_batch_noalloc(const flash_params* p, const int32_t* index,
                                         int64_t n_indexed, int64_t n_queries, int64_t nnz,
                                         const int64_t* q_row_ptr, const int32_t* q_col_idx,
                                         const int32_t* self_ids, int32_t k, int32_t* out_ids,
@@ -450,7 +463,8 @@ FLASH_API int flash_query_batch_noalloc(const flash_params* p, const uint32_t* c
   if (r) return r;
   if ((r = check_query(c, n_indexed, n_queries, k))) return r;
   if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
-  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts))
+  if (n_queries > 0 && (r = check_index(index))) return r;
+  if (n_queries > 0 && (!out_ids || !out_counts))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t kb = keys_bytes(c, n_queries);
   const size_t need = kb + query_ws_bytes(c, n_queries);
@@ -466,12 +480,12 @@ FLASH_API int flash_query_batch_noalloc(const flash_params* p, const uint32_t* c
   const QueryWs w = query_ws_carve(c, n_queries, ws + kb);
   e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k, nullptr, out_ids,
+  e = launch_query(c, index, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k, nullptr, out_ids,
                    out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
-FLASH_API int flash_query_keys_mixed(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_query_keys_mixed(const flash_params* p, const int32_t* index,
                                      int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                                      const int32_t* self_ids, const int32_t* k_per_query, int32_t k_max,
                                      int32_t* out_ids, int32_t* out_counts, void* workspace,
@@ -480,18 +494,19 @@ FLASH_API int flash_query_keys_mixed(const flash_params* p, const uint32_t* coun
   int r = make_cfg(p, &c);
   if (r) return r;
   if ((r = check_query(c, n_indexed, n_queries, k_max))) return r;
-  if (n_queries > 0 && (!counts || !ids || !qkeys || !out_ids || !out_counts || !k_per_query))
+  if (n_queries > 0 && (r = check_index(index))) return r;
+  if (n_queries > 0 && (!qkeys || !out_ids || !out_counts || !k_per_query))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t need = query_ws_bytes(c, n_queries);
   if (!workspace || workspace_bytes < need)
     return fail(FLASH_ENOSPC, "workspace smaller than flash_workspace_bytes(FLASH_OP_QUERY_KEYS)");
   const QueryWs w = query_ws_carve(c, n_queries, workspace);
-  hipError_t e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
+  hipError_t e = launch_query(c, index, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0,
                               k_max, k_per_query, out_ids, out_counts, w, (hipStream_t)stream);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
-FLASH_API int flash_query_batch_mixed(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_query_batch_mixed(const flash_params* p, const int32_t* index,
                                       int64_t n_indexed, int64_t n_queries, int64_t nnz,
                                       const int64_t* q_row_ptr, const int32_t* q_col_idx,
                                       const int32_t* self_ids, const int32_t* k_per_query,
@@ -502,7 +517,8 @@ FLASH_API int flash_query_batch_mixed(const flash_params* p, const uint32_t* cou
   if (r) return r;
   if ((r = check_query(c, n_indexed, n_queries, k_max))) return r;
   if ((r = check_csr(n_queries, nnz, q_row_ptr, q_col_idx))) return r;
-  if (n_queries > 0 && (!counts || !ids || !out_ids || !out_counts || !k_per_query))
+  if (n_queries > 0 && (r = check_index(index))) return r;
+  if (n_queries > 0 && (!out_ids || !out_counts || !k_per_query))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t kb = keys_bytes(c, n_queries);
   const size_t need = kb + query_ws_bytes(c, n_queries);
@@ -514,14 +530,14 @@ FLASH_API int flash_query_batch_mixed(const flash_params* p, const uint32_t* cou
   const QueryWs w = query_ws_carve(c, n_queries, (char*)workspace + kb);
   hipError_t e = launch_doph_hash(c, n_queries, nnz, q_row_ptr, q_col_idx, qkeys, nullptr, w.ovf_len + 2, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_query(c, counts, ids, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k_max,
+  e = launch_query(c, index, n_indexed, n_queries, qkeys, self_ids, self_ids ? 1 : 0, k_max,
                    k_per_query, out_ids, out_counts, w, s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
 
 FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz,
                               const int64_t* row_ptr, const int32_t* col_idx, int32_t k,
-                              uint32_t* counts, int32_t* ids, int32_t* out_ids, int32_t* out_counts,
+                              int32_t* index, int32_t* out_ids, int32_t* out_counts,
                               void* workspace, size_t workspace_bytes, void* stream) {
   Cfg c;
   int r = make_cfg(p, &c);
@@ -529,7 +545,8 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   if ((r = check_rows(c, n_rows, true))) return r;
   if ((r = check_csr(n_rows, nnz, row_ptr, col_idx))) return r;
   if ((r = check_query(c, n_rows, n_rows, k))) return r;
-  if (!counts || !ids || (n_rows > 0 && (!out_ids || !out_counts)))
+  if ((r = check_index(index))) return r;
+  if (n_rows > 0 && (!out_ids || !out_counts))
     return fail(FLASH_EINVAL, "NULL array");
   const size_t kb = keys_bytes(c, n_rows);
   const size_t ins = insert_ws_bytes(c, n_rows), qry = query_ws_bytes(c, n_rows);
@@ -541,9 +558,9 @@ FLASH_API int flash_knn_graph(const flash_params* p, int64_t n_rows, int64_t nnz
   char* rest = (char*)workspace + kb;
   hipError_t e = launch_doph_hash(c, n_rows, nnz, row_ptr, col_idx, keys, nullptr, nullptr, s);
   if (e != hipSuccess) return hip_fail(e, "doph_hash");
-  e = launch_insert(c, n_rows, keys, 0u, false, counts, ids, insert_ws_carve(c, n_rows, rest), s);
+  e = launch_insert(c, n_rows, keys, 0u, false, index, insert_ws_carve(c, n_rows, rest), s);
   if (e != hipSuccess) return hip_fail(e, "reservoir_insert");
-  e = launch_query(c, counts, ids, n_rows, n_rows, keys, nullptr, 2, k, nullptr, out_ids, out_counts,
+  e = launch_query(c, index, n_rows, n_rows, keys, nullptr, 2, k, nullptr, out_ids, out_counts,
                    query_ws_carve(c, n_rows, rest), s);
   return e == hipSuccess ? FLASH_OK : hip_fail(e, "count_topk");
 }
@@ -580,7 +597,7 @@ FLASH_API int flash_set_tuning(const flash_tuning* t) {
   return FLASH_OK;
 }
 
-FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* counts, const int32_t* ids,
+FLASH_API int flash_autotune_query_batch(const flash_params* p, const int32_t* index,
                                          int64_t n_indexed, int64_t n_queries, int64_t nnz,
                                          const int64_t* q_row_ptr, const int32_t* q_col_idx,
                                          const int32_t* self_ids, const int32_t* k_per_query,
@@ -593,10 +610,10 @@ FLASH_API int flash_autotune_query_batch(const flash_params* p, const uint32_t* 
   hipStream_t s = (hipStream_t)stream;
   auto run_once = [&]() {
     return k_per_query
-               ? flash_query_batch_mixed(p, counts, ids, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx,
+               ? flash_query_batch_mixed(p, index, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx,
                                          self_ids, k_per_query, k_max, out_ids, out_counts, workspace,
                                          workspace_bytes, stream)
-               : flash_query_batch(p, counts, ids, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx, self_ids,
+               : flash_query_batch(p, index, n_indexed, n_queries, nnz, q_row_ptr, q_col_idx, self_ids,
                                    k_max, out_ids, out_counts, workspace, workspace_bytes, stream);
   };
   hipEvent_t e0 = nullptr, e1 = nullptr;

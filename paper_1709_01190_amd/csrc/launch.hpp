@@ -17,7 +17,13 @@ struct Cfg {
   bool shared;     // reservoirs shared through a seeded map (Sec. 3.5)
   uint32_t s_r;    // seed of that map
   uint64_t P;      // reservoirs: L * M, or the shared pool
+  uint32_t S;      // words per reservoir in the index: header + R slots, rounded up to 128 bytes
 };
+
+// Reservoir layout in the index: word 0 holds the arrival count, words 1..3
+// are reserved, slot i is word kSlot0 + i; reservoirs are S words apart.
+constexpr uint32_t kSlot0 = 4;
+inline uint32_t reservoir_words(int R) { return ((uint32_t)R + kSlot0 + 31u) & ~31u; }
 
 // Reservoir of bucket m of table t (see flash.h, flash_params).
 __host__ __device__ __forceinline__ uint64_t reservoir_of(bool shared, uint32_t s_r, uint64_t P, uint32_t M,
@@ -66,7 +72,7 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws);
 // Rows of this batch get ids id_base + row.  append: merge into the
 // reservoirs and counts already in ids/counts (else they are replaced).
 hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t id_base, bool append,
-                         uint32_t* counts, int32_t* ids, const InsertWs& w, hipStream_t s);
+                         int32_t* index, const InsertWs& w, hipStream_t s);
 
 // ---- query (count_topk.hip)
 struct QueryWs {
@@ -76,7 +82,7 @@ struct QueryWs {
 size_t query_ws_bytes(const Cfg& c, int64_t n_queries);
 QueryWs query_ws_carve(const Cfg& c, int64_t n_queries, void* ws);
 // self_mode: 0 = none, 1 = self_ids array, 2 = query index is its own id
-hipError_t launch_query(const Cfg& c, const uint32_t* counts, const int32_t* ids,
+hipError_t launch_query(const Cfg& c, const int32_t* index,
                         int64_t n_indexed, int64_t n_queries, const uint32_t* qkeys,
                         const int32_t* self_ids, int self_mode, int32_t k, const int32_t* k_per_query,
                         int32_t* out_ids, int32_t* out_counts, const QueryWs& w, hipStream_t s);
@@ -89,6 +95,8 @@ hipError_t launch_rerank(int measure, int64_t n_indexed, int64_t nnz, const int6
 
 // ---- misc
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
+// p[i * stride] = v for i < n
+hipError_t launch_fill_strided_u32(uint32_t* p, uint64_t n, uint32_t stride, uint32_t v, hipStream_t s);
 
 // Lets `kernel` launch with `bytes` of dynamic LDS (above the 64 KiB
 // default).  The attribute is set once per kernel and size, not on every

@@ -41,6 +41,12 @@ __global__ void fill_u32_kernel(uint32_t* p, uint64_t n, uint32_t v) {
     p[i] = v;
 }
 
+__global__ void fill_strided_u32_kernel(uint32_t* p, uint64_t n, uint32_t stride, uint32_t v) {
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * blockDim.x)
+    p[i * stride] = v;
+}
+
 constexpr uint32_t kChunk = 16384;  // buckets per LDS histogram (64 KiB)
 constexpr int kPartThreads = 512;
 
@@ -270,11 +276,12 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
 }
 
 struct SelectArgs {
-  uint32_t* counts;        // in (when appending: the index's counts) and out
+  int32_t* index;          // reservoir b: count at index[b * S] (in when appending, and out),
+                           // slot i at index[b * S + kSlot0 + i]
+  uint32_t S;
   const uint32_t* newcnt;  // the batch's arrivals per bucket
   const uint32_t* seg;     // their first staged slot
   const int32_t* staged;
-  int32_t* ids;
   uint4* work;          // [nb] {bucket, first staged slot, candidates, old slots}
                         // of the large buckets, from the back
   uint32_t* wl_len;     // [2] [1]: large buckets listed ([0] unused)
@@ -282,14 +289,14 @@ struct SelectArgs {
   uint64_t s_p;
   uint32_t M;
   int R;
-  int append;           // 1: merge with the reservoirs already in ids/counts
+  int append;           // 1: merge with the reservoirs already in the index
 };
 
 // Candidate i of bucket bk: its first `occ` are the ids already in the
 // reservoir (appending), the rest the batch's arrivals.
 __device__ __forceinline__ uint32_t candidate(const SelectArgs& a, uint64_t bk, uint32_t start, uint32_t occ,
                                               uint32_t i) {
-  return i < occ ? (uint32_t)a.ids[bk * (uint64_t)a.R + i] : (uint32_t)a.staged[start + i - occ];
+  return i < occ ? (uint32_t)a.index[bk * (uint64_t)a.S + kSlot0 + i] : (uint32_t)a.staged[start + i - occ];
 }
 
 constexpr uint32_t kMid = 64;  // arrivals handled by one wave in registers
@@ -353,7 +360,7 @@ __device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, ui
     const bool live = has && sl < bn;
     const uint64_t v = live ? priority(a.s_p, t, candidate(a, bb, bs, bo, sl)) : ~0ull;
     const uint64_t sorted = segment_bitonic_sort<SEG>(v);
-    if (live && sl < R) a.ids[bb * R + sl] = (int32_t)(uint32_t)sorted;
+    if (live && sl < R) a.index[bb * a.S + kSlot0 + sl] = (int32_t)(uint32_t)sorted;
   }
 }
 
@@ -368,11 +375,11 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
   const bool in = bk < a.n_buckets;
   const uint32_t R = (uint32_t)a.R;
   const uint32_t nn = in ? a.newcnt[bk] : 0u;
-  const uint32_t old = (in && a.append) ? a.counts[bk] : 0u;
+  const uint32_t old = (in && a.append) ? (uint32_t)a.index[bk * (uint64_t)a.S] : 0u;
   const uint32_t occ = old < R ? old : R;   // reservoir slots that take part
   const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
   const uint32_t start = in ? a.seg[bk] : 0u;
-  if (in) a.counts[bk] = old + nn;
+  if (in) a.index[bk * (uint64_t)a.S] = (int32_t)(old + nn);
   const bool big = n > kMid;
   const uint32_t pb = wave_append(&a.wl_len[1], big);
   if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, occ);
@@ -388,7 +395,7 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
       int r = 0;
 #pragma unroll
       for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i] || (pk[j] == pk[i] && j < i);
-      if (r < a.R) a.ids[bk * (uint64_t)a.R + r] = (int32_t)(uint32_t)pk[i];
+      if (r < a.R) a.index[bk * (uint64_t)a.S + kSlot0 + r] = (int32_t)(uint32_t)pk[i];
     }
   }
   // every lane of the wave is still here: the mid-size buckets, several per
@@ -455,7 +462,7 @@ __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
     // every candidate was read above: the reservoir can be overwritten
     const uint32_t keep = n < R ? n : R;
     for (uint32_t i = lane; i < keep; i += kWave)
-      a.ids[(uint64_t)bk * R + i] = (int32_t)(uint32_t)buf[i];
+      a.index[(uint64_t)bk * a.S + kSlot0 + i] = (int32_t)(uint32_t)buf[i];
     __syncthreads();
   }
 }
@@ -471,6 +478,12 @@ int grid_for(uint64_t n, int threads, int per_cu) {
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
   hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_strided_u32(uint32_t* p, uint64_t n, uint32_t stride, uint32_t v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_strided_u32_kernel, dim3(grid_for(n, 256, 8)), dim3(256), 0, s, p, n, stride, v);
   return hipGetLastError();
 }
 
@@ -545,10 +558,11 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
 }
 
 hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uint32_t id_base, bool append,
-                         uint32_t* counts, int32_t* ids, const InsertWs& w, hipStream_t s) {
+                         int32_t* index, const InsertWs& w, hipStream_t s) {
   const Geo g = geometry(c, n_rows);
   hipError_t e;
-  if (n_rows <= 0) return append ? hipSuccess : launch_fill_u32(counts, g.nb, 0u, s);
+  // (with rows, the select below writes every reservoir's count)
+  if (n_rows <= 0) return append ? hipSuccess : launch_fill_strided_u32((uint32_t*)index, g.nb, c.S, 0u, s);
   if ((e = launch_fill_u32(w.wl_len, 2, 0u, s)) != hipSuccess) return e;
   // table-major keys
   ShareMap sm;
@@ -585,11 +599,11 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
                      w.partoff, g.nb, g.n_slices, w.newcnt, w.seg);
   hipLaunchKernelGGL(part_scatter_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
   SelectArgs a;
-  a.counts = counts;
+  a.index = index;
+  a.S = c.S;
   a.newcnt = w.newcnt;
   a.seg = w.seg;
   a.staged = w.staged;
-  a.ids = ids;
   a.work = w.work;
   a.wl_len = w.wl_len;
   a.n_buckets = g.nb;

@@ -74,31 +74,32 @@ def lib():
     P = ctypes.POINTER(flash_params)
     sig = {
         "flash_check_params": [P],
-        "flash_index_elems": [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
+        "flash_index_layout": [P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint32),
+                               ctypes.POINTER(ctypes.c_uint64)],
         "flash_workspace_bytes": [ctypes.c_int, P, _I64, _I64, ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_size_t)],
         "flash_hash": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP],
-        "flash_insert_keys": [P, _I64, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
-        "flash_build_index": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
-        "flash_query_keys": [P, _VP, _VP, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP,
+        "flash_insert_keys": [P, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_build_index": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_query_keys": [P, _VP, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP,
                              ctypes.c_size_t, _VP],
-        "flash_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP,
+        "flash_query_batch": [P, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP,
                               _VP, _VP, ctypes.c_size_t, _VP],
-        "flash_query_batch_noalloc": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32,
+        "flash_query_batch_noalloc": [P, _VP, _I64, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32,
                                       _VP, _VP, _VP],
-        "flash_query_keys_mixed": [P, _VP, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP,
+        "flash_query_keys_mixed": [P, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32, _VP, _VP,
                                    _VP, ctypes.c_size_t, _VP],
-        "flash_query_batch_mixed": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.c_int32,
+        "flash_query_batch_mixed": [P, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP, ctypes.c_int32,
                                     _VP, _VP, _VP, ctypes.c_size_t, _VP],
-        "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP, _VP,
+        "flash_knn_graph": [P, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP, _VP,
                             ctypes.c_size_t, _VP],
-        "flash_insert_keys_append": [P, _I64, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
-        "flash_build_index_append": [P, _I64, _I64, _VP, _VP, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_insert_keys_append": [P, _I64, _VP, _I64, _VP, _VP, ctypes.c_size_t, _VP],
+        "flash_build_index_append": [P, _I64, _I64, _VP, _VP, _I64, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_rerank_exact": [ctypes.c_int, _I64, _I64, _VP, _VP, _I64, _I64, _VP, _VP, _VP, ctypes.c_int32,
                                ctypes.c_int32, _VP, _VP, _VP],
         "flash_get_tuning": [ctypes.POINTER(flash_tuning)],
         "flash_set_tuning": [ctypes.POINTER(flash_tuning)],
-        "flash_autotune_query_batch": [P, _VP, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP,
+        "flash_autotune_query_batch": [P, _VP, _I64, _I64, _I64, _VP, _VP, _VP, _VP,
                                        ctypes.c_int32, _VP, _VP, _VP, ctypes.c_size_t,
                                        ctypes.c_int32, _VP, ctypes.POINTER(flash_tuning),
                                        ctypes.POINTER(ctypes.c_float)],
@@ -159,10 +160,18 @@ def flash_check_params(p: flash_params) -> None:
     _check(lib().flash_check_params(ctypes.byref(p)))
 
 
-def flash_index_elems(p: flash_params) -> Tuple[int, int]:
-    a, b = ctypes.c_uint64(), ctypes.c_uint64()
-    _check(lib().flash_index_elems(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b)))
-    return a.value, b.value
+def flash_index_layout(p: flash_params) -> Tuple[int, int, int]:
+    """(P reservoirs, S words per reservoir, P * S words) of the index array."""
+    a, b, c = ctypes.c_uint64(), ctypes.c_uint32(), ctypes.c_uint64()
+    _check(lib().flash_index_layout(ctypes.byref(p), ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return a.value, b.value, c.value
+
+
+SLOT0 = 4  # word of a reservoir that holds its first slot (word 0: the arrival count)
+
+
+def _need_index(p, index):
+    _need(index, flash_index_layout(p)[2], (torch.int32,), "index")
 
 
 def flash_workspace_bytes(op: int, p: flash_params, n_rows: int = 0, n_queries: int = 0,
@@ -188,80 +197,72 @@ def flash_hash(p, row_ptr, col_idx, keys, codes=None, stream=None):
                             _p(keys), _p(codes), _s(stream)))
 
 
-def flash_insert_keys(p, keys, counts, ids, workspace, stream=None):
+def flash_insert_keys(p, keys, index, workspace, stream=None):
     n = keys.numel() // p.L
-    ce, ie = flash_index_elems(p)
-    _need(counts, ce, _U32, "counts")
-    _need(ids, ie, (torch.int32,), "ids")
-    _check(lib().flash_insert_keys(ctypes.byref(p), n, _p(keys), _p(counts), _p(ids),
+    _need_index(p, index)
+    _check(lib().flash_insert_keys(ctypes.byref(p), n, _p(keys), _p(index),
                                    _p(workspace), workspace.numel() * workspace.element_size(),
                                    _s(stream)))
 
 
-def flash_build_index(p, row_ptr, col_idx, counts, ids, workspace, keys_out=None, stream=None):
+def flash_build_index(p, row_ptr, col_idx, index, workspace, keys_out=None, stream=None):
     n = row_ptr.numel() - 1
-    ce, ie = flash_index_elems(p)
-    _need(counts, ce, _U32, "counts")
-    _need(ids, ie, (torch.int32,), "ids")
+    _need_index(p, index)
     _need(keys_out, n * p.L, _U32, "keys_out")
     _check(lib().flash_build_index(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx),
-                                   _p(counts), _p(ids), _p(keys_out), _p(workspace),
+                                   _p(index), _p(keys_out), _p(workspace),
                                    workspace.numel() * workspace.element_size(), _s(stream)))
 
 
-def flash_insert_keys_append(p, keys, id_base, counts, ids, workspace, stream=None):
+def flash_insert_keys_append(p, keys, id_base, index, workspace, stream=None):
     n = keys.numel() // p.L
-    ce, ie = flash_index_elems(p)
-    _need(counts, ce, _U32, "counts")
-    _need(ids, ie, (torch.int32,), "ids")
+    _need_index(p, index)
     _check(lib().flash_insert_keys_append(ctypes.byref(p), n, _p(keys) if n else None, id_base,
-                                          _p(counts), _p(ids), _p(workspace) if workspace is not None else None,
+                                          _p(index), _p(workspace) if workspace is not None else None,
                                           workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                           _s(stream)))
 
 
-def flash_build_index_append(p, row_ptr, col_idx, id_base, counts, ids, workspace, stream=None):
+def flash_build_index_append(p, row_ptr, col_idx, id_base, index, workspace, stream=None):
     n = row_ptr.numel() - 1
-    ce, ie = flash_index_elems(p)
-    _need(counts, ce, _U32, "counts")
-    _need(ids, ie, (torch.int32,), "ids")
+    _need_index(p, index)
     _check(lib().flash_build_index_append(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr) if n else None,
-                                          _p(col_idx) if col_idx.numel() else None, id_base, _p(counts), _p(ids),
+                                          _p(col_idx) if col_idx.numel() else None, id_base, _p(index),
                                           _p(workspace) if workspace is not None else None,
                                           workspace.numel() * workspace.element_size() if workspace is not None else 0,
                                           _s(stream)))
 
 
-def flash_query_keys(p, counts, ids, n_indexed, qkeys, k, out_ids, out_counts, workspace,
+def flash_query_keys(p, index, n_indexed, qkeys, k, out_ids, out_counts, workspace,
                      self_ids=None, stream=None):
     q = qkeys.numel() // p.L
     _need(out_ids, q * k, (torch.int32,), "out_ids")
     _need(out_counts, q * k, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
-    _check(lib().flash_query_keys(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q, _p(qkeys),
+    _check(lib().flash_query_keys(ctypes.byref(p), _p(index), n_indexed, q, _p(qkeys),
                                   _p(self_ids), k, _p(out_ids), _p(out_counts), _p(workspace),
                                   workspace.numel() * workspace.element_size(), _s(stream)))
 
 
-def flash_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
+def flash_query_batch(p, index, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
                       workspace, self_ids=None, stream=None):
     q = q_row_ptr.numel() - 1
     _need(out_ids, q * k, (torch.int32,), "out_ids")
     _need(out_counts, q * k, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
-    _check(lib().flash_query_batch(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+    _check(lib().flash_query_batch(ctypes.byref(p), _p(index), n_indexed, q,
                                    q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx), _p(self_ids),
                                    k, _p(out_ids), _p(out_counts), _p(workspace),
                                    workspace.numel() * workspace.element_size(), _s(stream)))
 
 
-def flash_query_batch_noalloc(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
+def flash_query_batch_noalloc(p, index, n_indexed, q_row_ptr, q_col_idx, k, out_ids, out_counts,
                               self_ids=None, stream=None):
     q = q_row_ptr.numel() - 1
     _need(out_ids, q * k, (torch.int32,), "out_ids")
     _need(out_counts, q * k, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
-    _check(lib().flash_query_batch_noalloc(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+    _check(lib().flash_query_batch_noalloc(ctypes.byref(p), _p(index), n_indexed, q,
                                            q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
                                            _p(self_ids), k, _p(out_ids), _p(out_counts), _s(stream)))
 
@@ -270,27 +271,27 @@ def flash_noalloc_scratch_bytes() -> int:
     return int(lib().flash_noalloc_scratch_bytes())
 
 
-def flash_query_keys_mixed(p, counts, ids, n_indexed, qkeys, k_per_query, k_max, out_ids,
+def flash_query_keys_mixed(p, index, n_indexed, qkeys, k_per_query, k_max, out_ids,
                            out_counts, workspace, self_ids=None, stream=None):
     q = qkeys.numel() // p.L
     _need(k_per_query, q, (torch.int32,), "k_per_query")
     _need(out_ids, q * k_max, (torch.int32,), "out_ids")
     _need(out_counts, q * k_max, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
-    _check(lib().flash_query_keys_mixed(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q, _p(qkeys),
+    _check(lib().flash_query_keys_mixed(ctypes.byref(p), _p(index), n_indexed, q, _p(qkeys),
                                         _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
                                         _p(out_counts), _p(workspace),
                                         workspace.numel() * workspace.element_size(), _s(stream)))
 
 
-def flash_query_batch_mixed(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
+def flash_query_batch_mixed(p, index, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
                             out_ids, out_counts, workspace, self_ids=None, stream=None):
     q = q_row_ptr.numel() - 1
     _need(k_per_query, q, (torch.int32,), "k_per_query")
     _need(out_ids, q * k_max, (torch.int32,), "out_ids")
     _need(out_counts, q * k_max, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
-    _check(lib().flash_query_batch_mixed(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+    _check(lib().flash_query_batch_mixed(ctypes.byref(p), _p(index), n_indexed, q,
                                          q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
                                          _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
                                          _p(out_counts), _p(workspace),
@@ -329,7 +330,7 @@ def flash_set_tuning(t: Optional[flash_tuning] = None, **fields) -> None:
     _check(lib().flash_set_tuning(ctypes.byref(t) if t is not None else None))
 
 
-def flash_autotune_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
+def flash_autotune_query_batch(p, index, n_indexed, q_row_ptr, q_col_idx, k_per_query, k_max,
                                out_ids, out_counts, workspace, self_ids=None, reps=3, stream=None):
     """Returns (best flash_tuning, its time in ms); the best is installed."""
     q = q_row_ptr.numel() - 1
@@ -338,7 +339,7 @@ def flash_autotune_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, 
     _need(out_counts, q * k_max, (torch.int32,), "out_counts")
     _need(self_ids, q, (torch.int32,), "self_ids")
     best, ms = flash_tuning(), ctypes.c_float(0.0)
-    _check(lib().flash_autotune_query_batch(ctypes.byref(p), _p(counts), _p(ids), n_indexed, q,
+    _check(lib().flash_autotune_query_batch(ctypes.byref(p), _p(index), n_indexed, q,
                                             q_col_idx.numel(), _p(q_row_ptr), _p(q_col_idx),
                                             _p(self_ids), _p(k_per_query), k_max, _p(out_ids),
                                             _p(out_counts), _p(workspace),
@@ -347,26 +348,30 @@ def flash_autotune_query_batch(p, counts, ids, n_indexed, q_row_ptr, q_col_idx, 
     return best, float(ms.value)
 
 
-def flash_knn_graph(p, row_ptr, col_idx, k, counts, ids, out_ids, out_counts, workspace,
+def flash_knn_graph(p, row_ptr, col_idx, k, index, out_ids, out_counts, workspace,
                     stream=None):
     n = row_ptr.numel() - 1
-    ce, ie = flash_index_elems(p)
-    _need(counts, ce, _U32, "counts")
-    _need(ids, ie, (torch.int32,), "ids")
+    _need_index(p, index)
     _need(out_ids, n * k, (torch.int32,), "out_ids")
     _need(out_counts, n * k, (torch.int32,), "out_counts")
     _check(lib().flash_knn_graph(ctypes.byref(p), n, col_idx.numel(), _p(row_ptr), _p(col_idx), k,
-                                 _p(counts), _p(ids), _p(out_ids), _p(out_counts), _p(workspace),
+                                 _p(index), _p(out_ids), _p(out_counts), _p(workspace),
                                  workspace.numel() * workspace.element_size(), _s(stream)))
 
 
 # ------------------------------------------------------------------ allocation helpers
 
 def alloc_index(p: flash_params, device="cuda"):
-    """(counts int32[L*M], ids int32[L*M*R]) tensors, uninitialised."""
-    ce, ie = flash_index_elems(p)
-    return (torch.empty(ce, dtype=torch.int32, device=device),
-            torch.empty(ie, dtype=torch.int32, device=device))
+    """The index array, int32[P * S], uninitialised (the build writes every header)."""
+    return torch.empty(flash_index_layout(p)[2], dtype=torch.int32, device=device)
+
+
+def index_parts(p: flash_params, index: torch.Tensor):
+    """Views of an index array: (arrival counts int32[P], slots int32[P][R]).  Slot j of
+    reservoir b is meaningful for j < min(count, R)."""
+    P, S, _ = flash_index_layout(p)
+    res = index.view(P, S)
+    return res[:, 0], res[:, SLOT0:SLOT0 + p.R]
 
 
 def alloc_workspace(op: int, p: flash_params, n_rows=0, n_queries=0, k=0, device="cuda"):

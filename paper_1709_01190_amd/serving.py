@@ -1,6 +1,6 @@
 """Serving loop for the FLASH query path: continuous batching over a resident index.
 
-The index (counts, ids) stays in HBM.  Requests are CSR batches of query rows
+The index array stays in HBM.  Requests are CSR batches of query rows
 with their own k.  Two servers share one interface:
 
 * ContinuousServer: a request is admitted as soon as it has arrived, a slot
@@ -81,11 +81,11 @@ class GpuExecutor:
     run), so a request in steady state only copies and launches; the admission
     budget bounds the memory of the requests in flight."""
 
-    def __init__(self, p, counts, ids, n_indexed, device="cuda"):
+    def __init__(self, p, index, n_indexed, device="cuda"):
         import torch
         from . import flash
         self._torch, self._flash = torch, flash
-        self.p, self.counts, self.ids, self.n_indexed = p, counts, ids, n_indexed
+        self.p, self.index, self.n_indexed = p, index, n_indexed
         self.device = torch.device(device)
         self.grows = 0   # buffers allocated or grown so far (a timed run should add none)
 
@@ -152,7 +152,7 @@ class GpuExecutor:
             rp_d.copy_(rp_h, non_blocking=True)
             ci_d.copy_(ci_h, non_blocking=True)
             if n > 0:
-                flash.flash_query_batch(self.p, self.counts, self.ids, self.n_indexed, rp_d,
+                flash.flash_query_batch(self.p, self.index, self.n_indexed, rp_d,
                                         ci_d[:nnz], k, oi, oc, ws, stream=s)
             oi_h = self._buf(slot, "oi_h", n * k, i32, True)
             oc_h = self._buf(slot, "oc_h", n * k, i32, True)

@@ -17,7 +17,8 @@ def test_build_and_query_replay_in_a_hip_graph(orc):
     K, L, b, R, k = 5, 32, 3, 64, 16
     p = flash.flash_params.make(K, L, b, R, seed=1)
     n = spec.n_rows
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
+    counts, ids = flash.index_parts(p, index)   # views of the index array
     keys = torch.empty(n * L, dtype=torch.int32, device="cuda")
     bws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=n)
     qws = flash.alloc_workspace(flash.OP_QUERY_KEYS, p, n_queries=n, k=k)
@@ -27,8 +28,8 @@ def test_build_and_query_replay_in_a_hip_graph(orc):
     s = torch.cuda.Stream()
 
     def step():
-        flash.flash_build_index(p, rp, ci, counts, ids, bws, keys_out=keys, stream=s)
-        flash.flash_query_keys(p, counts, ids, n, keys, k, oi, oc, qws, self_ids=sid, stream=s)
+        flash.flash_build_index(p, rp, ci, index, bws, keys_out=keys, stream=s)
+        flash.flash_query_keys(p, index, n, keys, k, oi, oc, qws, self_ids=sid, stream=s)
 
     s.wait_stream(torch.cuda.current_stream())
     with torch.cuda.stream(s):
@@ -37,7 +38,7 @@ def test_build_and_query_replay_in_a_hip_graph(orc):
     ref_i, ref_c, ref_n = oi.clone(), oc.clone(), counts.clone()
     occ = torch.clamp(ref_n.view(-1).long(), max=R)
     mask = torch.arange(R, device="cuda")[None, :] < occ[:, None]
-    ref_ids = ids.view(-1, R)[mask].clone()
+    ref_ids = ids[mask].clone()
 
     g = torch.cuda.CUDAGraph()
     with torch.cuda.graph(g, stream=s):
@@ -46,13 +47,13 @@ def test_build_and_query_replay_in_a_hip_graph(orc):
     for rep in range(3):
         oi.fill_(-7)
         oc.fill_(-7)
+        index.fill_(-3)
         counts.fill_(12345)
-        ids.fill_(-3)
         torch.cuda.synchronize()
         g.replay()
         torch.cuda.synchronize()
         assert torch.equal(oi, ref_i) and torch.equal(oc, ref_c), rep
-        assert torch.equal(counts, ref_n) and torch.equal(ids.view(-1, R)[mask], ref_ids), rep
+        assert torch.equal(counts, ref_n) and torch.equal(ids[mask], ref_ids), rep
     # the eager result itself against the oracle on sampled queries
     op = orc.params(K, L, b, R, seed=1)
     okeys = orc.doph(op, rp.cpu().numpy(), ci.cpu().numpy())

@@ -70,6 +70,12 @@ def fmix32_inverse(h):
     return int(h[0])
 
 
+def host_index(fl, p, index):
+    """(arrival counts uint32[P], slots int32[P * R]) of a device index array."""
+    cnt, slots = fl.index_parts(p, index)
+    return u32(cnt.contiguous()), i32(slots.contiguous()).reshape(-1)
+
+
 def occupied_equal(counts_a, ids_a, counts_b, ids_b, L, M, R):
     """counts equal and the occupied slots of every bucket equal."""
     ca = counts_a.reshape(L, M)
@@ -99,21 +105,21 @@ def gpu_hash(fl, p, rp, ci, codes=True, offset=0):
 def gpu_insert(fl, p, keys_np):
     import torch
     n = keys_np.shape[0]
-    counts, ids = fl.alloc_index(p)
+    index = fl.alloc_index(p)
     ws = fl.alloc_workspace(fl.OP_INSERT, p, n_rows=n)
-    fl.flash_insert_keys(p, dev(keys_np.astype(np.uint32), torch.int32), counts, ids, ws)
+    fl.flash_insert_keys(p, dev(keys_np.astype(np.uint32), torch.int32), index, ws)
     torch.cuda.synchronize()
-    return counts, ids
+    return index
 
 
-def gpu_query(fl, p, counts, ids, n_indexed, qkeys_np, k, self_ids=None):
+def gpu_query(fl, p, index, n_indexed, qkeys_np, k, self_ids=None):
     import torch
     q = qkeys_np.shape[0]
     oi = torch.empty(q * k, dtype=torch.int32, device="cuda")
     oc = torch.empty(q * k, dtype=torch.int32, device="cuda")
     ws = fl.alloc_workspace(fl.OP_QUERY_KEYS, p, n_queries=q, k=k)
     sd = dev(self_ids.astype(np.int32)) if self_ids is not None else None
-    fl.flash_query_keys(p, counts, ids, n_indexed, dev(qkeys_np.astype(np.uint32), torch.int32), k,
+    fl.flash_query_keys(p, index, n_indexed, dev(qkeys_np.astype(np.uint32), torch.int32), k,
                         oi, oc, ws, self_ids=sd)
     torch.cuda.synchronize()
     return i32(oi).reshape(q, k), i32(oc).reshape(q, k)
@@ -181,8 +187,8 @@ def test_insert_tiny_workload(fl, orc):
     keys = orc.doph(op, rp, ci)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(4, 16, 4, 32, seed=1)
-    counts, ids = gpu_insert(fl, p, keys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
 
 
 @pytest.mark.parametrize("R", [1, 4, 32, 256, 1024])
@@ -209,8 +215,8 @@ def test_insert_heavy_buckets(fl, orc, R):
     op = orc.params(K, L, b, R, seed=R + 3)
     ocounts, oids = orc.build_tables(op, km)
     p = fl.flash_params.make(K, L, b, R, seed=R + 3)
-    counts, ids = gpu_insert(fl, p, km)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+    index = gpu_insert(fl, p, km)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
 
 
 def test_insert_is_deterministic(fl):
@@ -221,9 +227,9 @@ def test_insert_is_deterministic(fl):
     M = 1 << (K * b)
     keys = (rng.zipf(1.3, size=(200000, L)) % M).astype(np.uint32)
     p = fl.flash_params.make(K, L, b, R, seed=9)
-    c1, i1 = gpu_insert(fl, p, keys)
-    c2, i2 = gpu_insert(fl, p, keys)
-    occupied_equal(u32(c1), i32(i1), u32(c2), i32(i2), L, M, R)
+    index1 = gpu_insert(fl, p, keys)
+    index2 = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index1), *host_index(fl, p, index2), L, M, R)
 
 
 # ------------------------------------------------------------------ query
@@ -236,24 +242,24 @@ def tiny_index(fl, orc):
     keys = orc.doph(op, rp, ci)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(4, 16, 4, 32, seed=1)
-    counts, ids = gpu_insert(fl, p, keys)
-    return p, op, rp, ci, keys, counts, ids, ocounts, oids
+    index = gpu_insert(fl, p, keys)
+    return p, op, rp, ci, keys, index, ocounts, oids
 
 
 @pytest.mark.parametrize("k", [1, 16, 100, 1024])
 def test_query_tiny_graph_mode(fl, orc, tiny_index, k):
     say("query tiny graph k", k)
-    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    p, op, rp, ci, keys, index, ocounts, oids = tiny_index
     n = keys.shape[0]
     self_ids = np.arange(n, dtype=np.int32)
-    oi, oc = gpu_query(fl, p, counts, ids, n, keys, k, self_ids)
+    oi, oc = gpu_query(fl, p, index, n, keys, k, self_ids)
     wi, wc = orc.query(op, ocounts, oids, keys, k, self_ids=self_ids)
     assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
 def test_query_mixed_keys_and_self(fl, orc, tiny_index):
     say("query mixed keys")
-    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    p, op, rp, ci, keys, index, ocounts, oids = tiny_index
     rng = np.random.default_rng(8)
     q = 3000
     qk = keys[rng.integers(0, keys.shape[0], size=q)].copy()
@@ -263,7 +269,7 @@ def test_query_mixed_keys_and_self(fl, orc, tiny_index):
     qk[5, 3] = (1 << 16) + 9  # out of range: ignored
     self_ids = rng.integers(-1, keys.shape[0], size=q).astype(np.int32)
     for sids in (None, self_ids):
-        oi, oc = gpu_query(fl, p, counts, ids, keys.shape[0], qk, 40, sids)
+        oi, oc = gpu_query(fl, p, index, keys.shape[0], qk, 40, sids)
         wi, wc = orc.query(op, ocounts, oids, qk, 40, self_ids=sids)
         assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
@@ -299,15 +305,15 @@ def test_query_overflow_table(fl, orc, tuned):
     op = orc.params(K, L, b, R, seed=4)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(K, L, b, R, seed=4)
-    counts, ids = gpu_insert(fl, p, keys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
     qk = keys[:700].copy()
     qk[100:400, 4:] = EMPTY     # small queries stay in the first pass
     wi, wc = orc.query(op, ocounts, oids, qk, 300, self_ids=np.arange(700, dtype=np.int32))
     for shape in STAGE_SHAPES:
         tuned(None)
         tuned(**shape)
-        oi, oc = gpu_query(fl, p, counts, ids, n, qk, 300, np.arange(700, dtype=np.int32))
+        oi, oc = gpu_query(fl, p, index, n, qk, 300, np.arange(700, dtype=np.int32))
         assert np.array_equal(oi, wi) and np.array_equal(oc, wc), shape
 
 
@@ -323,9 +329,9 @@ def test_query_top_k_among_thousands_of_ties(fl, orc, k):
     op = orc.params(K, L, b, R, seed=8)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(K, L, b, R, seed=8)
-    counts, ids = gpu_insert(fl, p, keys)
+    index = gpu_insert(fl, p, keys)
     wi, wc = orc.query(op, ocounts, oids, keys[:600], k, self_ids=np.arange(600, dtype=np.int32))
-    oi, oc = gpu_query(fl, p, counts, ids, n, keys[:600], k, np.arange(600, dtype=np.int32))
+    oi, oc = gpu_query(fl, p, index, n, keys[:600], k, np.arange(600, dtype=np.int32))
     assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
@@ -339,9 +345,9 @@ def test_query_many_tables(fl, orc):
     op = orc.params(K, L, b, R, seed=6)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(K, L, b, R, seed=6)
-    counts, ids = gpu_insert(fl, p, keys)
+    index = gpu_insert(fl, p, keys)
     wi, wc = orc.query(op, ocounts, oids, keys[:500], 64, self_ids=np.arange(500, dtype=np.int32))
-    oi, oc = gpu_query(fl, p, counts, ids, n, keys[:500], 64, np.arange(500, dtype=np.int32))
+    oi, oc = gpu_query(fl, p, index, n, keys[:500], 64, np.arange(500, dtype=np.int32))
     assert np.array_equal(oi, wi) and np.array_equal(oc, wc)
 
 
@@ -376,7 +382,7 @@ def test_filter_stage_edges(fl, orc, tuned, case):
     op = orc.params(K, L, b, R, seed=12)
     ocounts, oids = orc.build_tables(op, keys)
     p = fl.flash_params.make(K, L, b, R, seed=12)
-    counts, ids = gpu_insert(fl, p, keys)
+    index = gpu_insert(fl, p, keys)
     qk = keys[n - nq:] if case == "high_ids" else keys[:nq]
     sid = np.arange(n - nq, n, dtype=np.int32) if case == "high_ids" else np.arange(nq, dtype=np.int32)
     for k in ks:
@@ -384,18 +390,18 @@ def test_filter_stage_edges(fl, orc, tuned, case):
         for filt in (1, 0):
             tuned(None)
             tuned(query_filter=filt)
-            oi, oc = gpu_query(fl, p, counts, ids, n_indexed, qk, k, sid)
+            oi, oc = gpu_query(fl, p, index, n_indexed, qk, k, sid)
             assert np.array_equal(oi, wi) and np.array_equal(oc, wc), (case, k, filt)
 
 
 def test_query_launch_shape_does_not_change_results(fl, orc, tiny_index, tuned):
     say("query launch shapes")
-    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    p, op, rp, ci, keys, index, ocounts, oids = tiny_index
     n = keys.shape[0]
     ref = None
     for per_cu, filt in ((1, 1), (4, 0), (32, 1), (32, 0)):
         tuned(query_blocks_per_cu=per_cu, query_filter=filt)
-        out = gpu_query(fl, p, counts, ids, n, keys, 16, np.arange(n, dtype=np.int32))
+        out = gpu_query(fl, p, index, n, keys, 16, np.arange(n, dtype=np.int32))
         if ref is None:
             ref = out
         assert np.array_equal(out[0], ref[0]) and np.array_equal(out[1], ref[1])
@@ -411,60 +417,61 @@ def test_empty_batches_and_empty_rows(fl, orc):
     op = orc.params(4, 16, 4, 32, seed=1)
     rp0 = torch.zeros(1, dtype=torch.int64, device="cuda")
     ci0 = torch.zeros(0, dtype=torch.int32, device="cuda")
-    counts, ids = fl.alloc_index(p)
-    counts.fill_(5)
-    ids.fill_(9)
+    index = fl.alloc_index(p)
+    index.fill_(9)
+    fl.index_parts(p, index)[0].fill_(5)
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=0)
     keys0 = torch.zeros(0, dtype=torch.int32, device="cuda")
     fl.flash_hash(p, rp0, ci0, keys0)
-    fl.flash_insert_keys_append(p, keys0, 0, counts, ids, ws)
-    fl.flash_build_index_append(p, rp0, ci0, 0, counts, ids, ws)
+    fl.flash_insert_keys_append(p, keys0, 0, index, ws)
+    fl.flash_build_index_append(p, rp0, ci0, 0, index, ws)
     torch.cuda.synchronize()
-    assert (i32(counts) == 5).all() and (i32(ids) == 9).all()
-    fl.flash_build_index(p, rp0, ci0, counts, ids, ws)
+    hc, hs = host_index(fl, p, index)
+    assert (hc == 5).all() and (hs == 9).all()
+    fl.flash_build_index(p, rp0, ci0, index, ws)
     torch.cuda.synchronize()
-    assert (i32(counts) == 0).all()
+    assert (host_index(fl, p, index)[0] == 0).all()
     # a real index, then empty query batches and a batch of empty queries
     from paper_1709_01190_amd import datagen
     spec = datagen.scaled(datagen.TINY, 2000)
     rp, ci = datagen.make_rows(spec, 1)
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
-    fl.flash_build_index(p, rp.cuda(), ci.cuda(), counts, ids, ws)
+    fl.flash_build_index(p, rp.cuda(), ci.cuda(), index, ws)
     torch.cuda.synchronize()
-    snap = (i32(counts).copy(), i32(ids).copy())
+    snap = i32(index).copy()
     k = 8
     sentinel = torch.full((4 * k,), 77, dtype=torch.int32, device="cuda")
     oi, oc = sentinel.clone(), sentinel.clone()
     qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=0, k=k)
-    fl.flash_query_keys(p, counts, ids, spec.n_rows, keys0, k, oi, oc, qws)
-    fl.flash_query_batch(p, counts, ids, spec.n_rows, rp0, ci0, k, oi, oc, qws)
-    fl.flash_query_batch_mixed(p, counts, ids, spec.n_rows, rp0, ci0,
+    fl.flash_query_keys(p, index, spec.n_rows, keys0, k, oi, oc, qws)
+    fl.flash_query_batch(p, index, spec.n_rows, rp0, ci0, k, oi, oc, qws)
+    fl.flash_query_batch_mixed(p, index, spec.n_rows, rp0, ci0,
                                torch.zeros(0, dtype=torch.int32, device="cuda"), k, oi, oc, qws)
     gws = fl.alloc_workspace(fl.OP_KNN_GRAPH, p, n_rows=0, k=k)
-    c2, i2 = fl.alloc_index(p)
-    fl.flash_knn_graph(p, rp0, ci0, k, c2, i2, oi, oc, gws)
+    index2 = fl.alloc_index(p)
+    fl.flash_knn_graph(p, rp0, ci0, k, index2, oi, oc, gws)
     fl.flash_rerank_exact(fl.SIM_COSINE, rp.cuda(), ci.cuda(), rp0, ci0,
                           torch.zeros((0, k), dtype=torch.int32, device="cuda"), k, oi, oc)
     torch.cuda.synchronize()
     assert (i32(oi) == 77).all() and (i32(oc) == 77).all()
-    assert (i32(c2) == 0).all()
+    assert (host_index(fl, p, index2)[0] == 0).all()
     q = 4
     qrp = torch.zeros(q + 1, dtype=torch.int64, device="cuda")   # four rows without columns
     qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=k)
-    fl.flash_query_batch(p, counts, ids, spec.n_rows, qrp, ci0, k, oi, oc, qws)
+    fl.flash_query_batch(p, index, spec.n_rows, qrp, ci0, k, oi, oc, qws)
     torch.cuda.synchronize()
     wi, wc = orc.query(op, *orc.build_tables(op, orc.doph(op, rp.numpy(), ci.numpy())),
                        orc.doph(op, qrp.cpu().numpy(), np.zeros(0, np.int32)), k)
     assert (wi == -1).all() and (wc == 0).all()
     assert np.array_equal(i32(oi).reshape(q, k), wi.reshape(q, k))
     assert np.array_equal(i32(oc).reshape(q, k), wc.reshape(q, k))
-    assert np.array_equal(i32(counts), snap[0]) and np.array_equal(i32(ids), snap[1])
+    assert np.array_equal(i32(index), snap)
     # an index of rows without columns holds nothing
     rpe = torch.zeros(101, dtype=torch.int64, device="cuda")
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=100)
-    fl.flash_build_index(p, rpe, ci0, counts, ids, ws)
+    fl.flash_build_index(p, rpe, ci0, index, ws)
     torch.cuda.synchronize()
-    assert (i32(counts) == 0).all()
+    assert (host_index(fl, p, index)[0] == 0).all()
 
 
 # ------------------------------------------------------------------ whole path
@@ -472,15 +479,15 @@ def test_empty_batches_and_empty_rows(fl, orc):
 def _gpu_graph(fl, p, rp, ci, k):
     import torch
     n = rp.shape[0] - 1
-    counts, ids = fl.alloc_index(p)
+    index = fl.alloc_index(p)
     ws = fl.alloc_workspace(fl.OP_KNN_GRAPH, p, n_rows=n, k=k)
     oi = torch.empty(n * k, dtype=torch.int32, device="cuda")
     oc = torch.empty(n * k, dtype=torch.int32, device="cuda")
     rp_d = rp if hasattr(rp, "is_cuda") else dev(rp)
     ci_d = ci if hasattr(ci, "is_cuda") else dev(ci)
-    fl.flash_knn_graph(p, rp_d, ci_d, k, counts, ids, oi, oc, ws)
+    fl.flash_knn_graph(p, rp_d, ci_d, k, index, oi, oc, ws)
     torch.cuda.synchronize()
-    return counts, ids, oi.view(n, k), oc.view(n, k)
+    return index, oi.view(n, k), oc.view(n, k)
 
 
 def test_knn_graph_tiny_end_to_end(fl, orc):
@@ -488,9 +495,9 @@ def test_knn_graph_tiny_end_to_end(fl, orc):
     say("knn graph tiny")
     rp, ci = (a.numpy() for a in datagen.make_rows(datagen.TINY, 1))
     p = fl.flash_params.make(4, 16, 4, 32, seed=1)
-    counts, ids, oi, oc = _gpu_graph(fl, p, rp, ci, 16)
+    index, oi, oc = _gpu_graph(fl, p, rp, ci, 16)
     okeys, ocounts, oids, wi, wc = orc.knn_graph(orc.params(4, 16, 4, 32, seed=1), rp, ci, 16)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 16, 1 << 16, 32)
     assert np.array_equal(i32(oi), wi) and np.array_equal(i32(oc), wc)
     r, nq = orc.recall_at_k(rp, ci, datagen.TINY.n_cols, np.arange(rp.shape[0] - 1), i32(oi))
     say(f"tiny R@16 (Jaccard gold standard) = {r:.4f} over {nq} queries")
@@ -508,15 +515,15 @@ def test_query_batch_from_csr(fl, orc):
     ocounts, oids = orc.build_tables(op, okeys)
     wi, wc = orc.query(op, ocounts, oids, orc.doph(op, qrp, qci), 25)
     p = fl.flash_params.make(4, 16, 4, 32, seed=1)
-    counts, ids = fl.alloc_index(p)
+    index = fl.alloc_index(p)
     n = rp.shape[0] - 1
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=n)
-    fl.flash_build_index(p, dev(rp), dev(ci), counts, ids, ws)
+    fl.flash_build_index(p, dev(rp), dev(ci), index, ws)
     q = qrp.shape[0] - 1
     oi = torch.empty(q * 25, dtype=torch.int32, device="cuda")
     oc = torch.empty(q * 25, dtype=torch.int32, device="cuda")
     qws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=25)
-    fl.flash_query_batch(p, counts, ids, n, dev(qrp), dev(qci), 25, oi, oc, qws)
+    fl.flash_query_batch(p, index, n, dev(qrp), dev(qci), 25, oi, oc, qws)
     torch.cuda.synchronize()
     assert np.array_equal(i32(oi).reshape(q, 25), wi) and np.array_equal(i32(oc).reshape(q, 25), wc)
 
@@ -534,7 +541,7 @@ def test_url_full_size_graph(fl, orc):
     n = spec.n_rows
     K, L, b, R, k = 5, 32, 3, 64, 64
     p = fl.flash_params.make(K, L, b, R, seed=1)
-    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
+    index, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
     gkeys = torch.empty(n * L, dtype=torch.int32, device="cuda")
     fl.flash_hash(p, rp_d, ci_d, gkeys)
     torch.cuda.synchronize()
@@ -544,7 +551,7 @@ def test_url_full_size_graph(fl, orc):
     assert np.array_equal(u32(gkeys).reshape(n, L), okeys)
     occ = np.minimum(ocounts, R)
     assert occ.mean() > 0.6 * R, "the full-bucket regime is not reached"
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
     assert np.array_equal(i32(oi).reshape(n, k), wi) and np.array_equal(i32(oc).reshape(n, k), wc)
 
 
@@ -559,7 +566,7 @@ def test_webspam_full_size_graph(fl, orc):
     n = spec.n_rows
     K, L, b, R, k = 4, 64, 4, 128, 128
     p = fl.flash_params.make(K, L, b, R, seed=1)
-    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
+    index, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, k)
     gkeys = torch.empty(n * L, dtype=torch.int32, device="cuda")
     fl.flash_hash(p, rp_d, ci_d, gkeys)
     torch.cuda.synchronize()
@@ -569,7 +576,7 @@ def test_webspam_full_size_graph(fl, orc):
     okeys = orc.doph(op, rp, ci)
     assert np.array_equal(u32(gkeys).reshape(n, L), okeys)
     ocounts, oids = orc.build_tables(op, okeys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
     wi, wc = orc.query(op, ocounts, oids, okeys, k, self_ids=np.arange(n, dtype=np.int32))
     assert np.array_equal(i32(oi).reshape(n, k), wi) and np.array_equal(i32(oc).reshape(n, k), wc)
 
@@ -579,7 +586,7 @@ def test_query_mixed_k(fl, orc, tiny_index):
     # padded past it
     import torch
     say("query mixed k")
-    p, op, rp, ci, keys, counts, ids, ocounts, oids = tiny_index
+    p, op, rp, ci, keys, index, ocounts, oids = tiny_index
     rng = np.random.default_rng(12)
     q = 2500
     qk = keys[rng.integers(0, keys.shape[0], size=q)]
@@ -590,7 +597,7 @@ def test_query_mixed_k(fl, orc, tiny_index):
     oi = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
     oc = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
     ws = fl.alloc_workspace(fl.OP_QUERY_KEYS, p, n_queries=q, k=k_max)
-    fl.flash_query_keys_mixed(p, counts, ids, keys.shape[0], dev(qk.astype(np.uint32), torch.int32),
+    fl.flash_query_keys_mixed(p, index, keys.shape[0], dev(qk.astype(np.uint32), torch.int32),
                               dev(kq), k_max, oi, oc, ws)
     torch.cuda.synchronize()
     gi, gc = i32(oi).reshape(q, k_max), i32(oc).reshape(q, k_max)
@@ -630,13 +637,13 @@ def _mixed_expected(orc, op, ocounts, oids, okeys_q, kq, k_max, self_ids=None):
     return wi, wc
 
 
-def _gpu_batch_mixed(fl, p, counts, ids, n_indexed, qrp_d, qci_d, kq, k_max):
+def _gpu_batch_mixed(fl, p, index, n_indexed, qrp_d, qci_d, kq, k_max):
     import torch
     q = qrp_d.numel() - 1
     oi = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
     oc = torch.empty(q * k_max, dtype=torch.int32, device="cuda")
     ws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=k_max)
-    fl.flash_query_batch_mixed(p, counts, ids, n_indexed, qrp_d, qci_d, dev(kq.numpy()), k_max, oi, oc, ws)
+    fl.flash_query_batch_mixed(p, index, n_indexed, qrp_d, qci_d, dev(kq.numpy()), k_max, oi, oc, ws)
     torch.cuda.synchronize()
     return i32(oi).reshape(q, k_max), i32(oc).reshape(q, k_max)
 
@@ -653,21 +660,21 @@ def saturated_index(fl, orc):
     rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
     K, L, b, R = 2, 32, 4, 256
     p = fl.flash_params.make(K, L, b, R, seed=1)
-    counts, ids = fl.alloc_index(p)
+    index = fl.alloc_index(p)
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
-    fl.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
+    fl.flash_build_index(p, rp_d, ci_d, index, ws)
     torch.cuda.synchronize()
     op = orc.params(K, L, b, R, seed=1)
     okeys = orc.doph(op, rp_d.cpu().numpy(), ci_d.cpu().numpy())
     ocounts, oids = orc.build_tables(op, okeys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
-    return spec, p, op, counts, ids, ocounts, oids
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << (K * b), R)
+    return spec, p, op, index, ocounts, oids
 
 
 def test_uneven_batch_every_launch_shape(fl, orc, saturated_index, tuned):
     # heavy-tailed query sizes (5 .. 50,000 nonzeros) and mixed k in one
     # batch, under every stage layout, workgroup width and hash schedule
-    spec, p, op, counts, ids, ocounts, oids = saturated_index
+    spec, p, op, index, ocounts, oids = saturated_index
     qrp_d, qci_d, kq = _uneven_queries(spec, 3000)
     qrp, qci = qrp_d.cpu().numpy(), qci_d.cpu().numpy()
     assert int((qrp[1:] - qrp[:-1]).max()) > 5000          # the tail is present
@@ -676,27 +683,27 @@ def test_uneven_batch_every_launch_shape(fl, orc, saturated_index, tuned):
         say("uneven batch", shape)
         tuned(None)
         tuned(**shape)
-        gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+        gi, gc = _gpu_batch_mixed(fl, p, index, spec.n_rows, qrp_d, qci_d, kq, 100)
         assert np.array_equal(gi, wi) and np.array_equal(gc, wc), shape
 
 
 def test_autotune_query_batch(fl, orc, saturated_index, tuned):
     import torch
     say("autotune")
-    spec, p, op, counts, ids, ocounts, oids = saturated_index
+    spec, p, op, index, ocounts, oids = saturated_index
     qrp_d, qci_d, kq = _uneven_queries(spec, 2000)
     q = 2000
     oi = torch.empty(q * 100, dtype=torch.int32, device="cuda")
     oc = torch.empty_like(oi)
     ws = fl.alloc_workspace(fl.OP_QUERY, p, n_queries=q, k=100)
-    best, ms = fl.flash_autotune_query_batch(p, counts, ids, spec.n_rows, qrp_d, qci_d,
+    best, ms = fl.flash_autotune_query_batch(p, index, spec.n_rows, qrp_d, qci_d,
                                              dev(kq.numpy()), 100, oi, oc, ws, reps=2)
     torch.cuda.synchronize()
     assert ms > 0 and fl.flash_get_tuning().as_dict() == best.as_dict()
     wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp_d.cpu().numpy(), qci_d.cpu().numpy()),
                              kq.numpy(), 100)
     assert np.array_equal(i32(oi).reshape(q, 100), wi) and np.array_equal(i32(oc).reshape(q, 100), wc)
-    gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+    gi, gc = _gpu_batch_mixed(fl, p, index, spec.n_rows, qrp_d, qci_d, kq, 100)
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
 
 
@@ -712,22 +719,22 @@ def test_clicklog_full_size_uneven(fl, orc):
     rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
     K, L, b, R = 4, 32, 4, 256
     p = fl.flash_params.make(K, L, b, R, seed=1)
-    counts, ids = fl.alloc_index(p)
+    index = fl.alloc_index(p)
     ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=spec.n_rows)
-    fl.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
+    fl.flash_build_index(p, rp_d, ci_d, index, ws)
     torch.cuda.synchronize()
     del ws
     nq = 100_000
     qrp_d, qci_d, kq = _uneven_queries(spec, nq)
     sizes = (qrp_d[1:] - qrp_d[:-1]).cpu().numpy()
     assert (sizes > 1000).sum() >= 100 and sizes.max() > 10_000   # the tail is present
-    gi, gc = _gpu_batch_mixed(fl, p, counts, ids, spec.n_rows, qrp_d, qci_d, kq, 100)
+    gi, gc = _gpu_batch_mixed(fl, p, index, spec.n_rows, qrp_d, qci_d, kq, 100)
     op = orc.params(K, L, b, R, seed=1)
     okeys = orc.doph(op, rp_d.cpu().numpy(), ci_d.cpu().numpy())
     del rp_d, ci_d
     ocounts, oids = orc.build_tables(op, okeys)
     del okeys
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 16, R)
     wi, wc = _mixed_expected(orc, op, ocounts, oids, orc.doph(op, qrp_d.cpu().numpy(), qci_d.cpu().numpy()),
                              kq.numpy(), 100)
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
@@ -741,31 +748,32 @@ def _append_batches(fl, p, keys_np, cuts, order, first_fresh=False):
     flash_insert_keys, which numbers rows from 0, so that range must start at
     row 0, and the rest appended)."""
     import torch
-    counts, ids = fl.alloc_index(p)
-    counts.zero_()
+    index = fl.alloc_index(p)
+    index.fill_(-7)                        # slots past the occupancy are never read
+    fl.index_parts(p, index)[0].zero_()
     for j, i in enumerate(order):
         lo, hi = cuts[i], cuts[i + 1]
         part = dev(np.ascontiguousarray(keys_np[lo:hi]).astype(np.uint32), torch.int32)
         ws = fl.alloc_workspace(fl.OP_INSERT, p, n_rows=hi - lo) if hi > lo else None
         if first_fresh and j == 0:
             assert lo == 0
-            fl.flash_insert_keys(p, part, counts, ids, ws)
+            fl.flash_insert_keys(p, part, index, ws)
         else:
-            fl.flash_insert_keys_append(p, part, lo, counts, ids, ws)
+            fl.flash_insert_keys_append(p, part, lo, index, ws)
     torch.cuda.synchronize()
-    return counts, ids
+    return index
 
 
 def test_append_batches_equal_one_build(fl, orc, tiny_index):
     # any batching and order of appends gives the one-shot build's tables
     say("append tiny")
-    p, op, rp, ci, keys, counts0, ids0, ocounts, oids = tiny_index
+    p, op, rp, ci, keys, index0, ocounts, oids = tiny_index
     n = keys.shape[0]
     cuts = [0, 3000, 3001, 3001, 7000, n]
     for order, fresh in (([0, 1, 2, 3, 4], False), ([3, 0, 4, 2, 1], False), ([0, 4, 2, 3, 1], True)):
         say("append order", order, "fresh first" if fresh else "")
-        c, i = _append_batches(fl, p, keys, cuts, order, first_fresh=fresh)
-        occupied_equal(u32(c), i32(i), ocounts.reshape(-1), oids.reshape(-1), p.L, p.M, p.R)
+        index = _append_batches(fl, p, keys, cuts, order, first_fresh=fresh)
+        occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), p.L, p.M, p.R)
 
 
 @pytest.mark.parametrize("R", [1, 4, 32, 256])
@@ -790,8 +798,8 @@ def test_append_into_full_reservoirs(fl, orc, R):
     ocounts, oids = orc.build_tables(op, km)
     p = fl.flash_params.make(K, L, b, R, seed=R + 11)
     cuts = [0, 7, 500, 20000, n // 2, n]
-    c, i = _append_batches(fl, p, km, cuts, [2, 0, 4, 1, 3])
-    occupied_equal(u32(c), i32(i), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+    index = _append_batches(fl, p, km, cuts, [2, 0, 4, 1, 3])
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
 
 
 def test_append_csr_batches_then_query(fl, orc):
@@ -807,18 +815,19 @@ def test_append_csr_batches_then_query(fl, orc):
     op = orc.params(K, L, b, R, seed=1)
     okeys = orc.doph(op, rp, ci)
     ocounts, oids = orc.build_tables(op, okeys)
-    counts, ids = fl.alloc_index(p)
-    counts.zero_()
+    index = fl.alloc_index(p)
+    index.fill_(-7)
+    fl.index_parts(p, index)[0].zero_()
     cuts = [0, 50_000, 50_001, 90_000, spec.n_rows]
     for lo, hi in zip(cuts, cuts[1:]):
         brp = dev((rp[lo:hi + 1] - rp[lo]).astype(np.int64))
         bci = dev(ci[rp[lo]:rp[hi]])
         ws = fl.alloc_workspace(fl.OP_BUILD, p, n_rows=hi - lo)
-        fl.flash_build_index_append(p, brp, bci, lo, counts, ids, ws)
+        fl.flash_build_index_append(p, brp, bci, lo, index, ws)
     torch.cuda.synchronize()
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, 1 << 15, R)
     sample = np.arange(0, spec.n_rows, 97)
-    gi, gc = gpu_query(fl, p, counts, ids, spec.n_rows, okeys[sample], 20, sample.astype(np.int32))
+    gi, gc = gpu_query(fl, p, index, spec.n_rows, okeys[sample], 20, sample.astype(np.int32))
     wi, wc = orc.query(op, ocounts, oids, okeys[sample], 20, self_ids=sample.astype(np.int32))
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
 
@@ -919,18 +928,19 @@ def _shared_pair(fl, orc, K, L, b, R, seed, permille):
     p = fl.flash_params.make(K, L, b, R, seed=seed, share_permille=permille)
     op = orc.params(K, L, b, R, seed=seed, share_permille=permille)
     P = orc.pool_size(op)
-    assert fl.flash_index_elems(p) == (P, P * R)
+    S = fl.flash_index_layout(p)[1]
+    assert fl.flash_index_layout(p) == (P, S, P * S)
     return p, op, P
 
 
 @pytest.mark.parametrize("permille", [1, 100, 600])
 def test_shared_insert_tiny(fl, orc, tiny_index, permille):
     say("shared insert tiny", permille)
-    _, _, rp, ci, keys, _, _, _, _ = tiny_index
+    _, _, rp, ci, keys, _, _, _ = tiny_index
     p, op, P = _shared_pair(fl, orc, 4, 16, 4, 32, 1, permille)
     ocounts, oids = orc.build_tables(op, keys)
-    counts, ids = gpu_insert(fl, p, keys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, 32)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 1, P, 32)
 
 
 @pytest.mark.parametrize("R", [4, 64, 300])
@@ -945,11 +955,11 @@ def test_shared_heavy_reservoirs(fl, orc, R):
     keys[rng.random((n, L)) < 0.02] = EMPTY
     p, op, P = _shared_pair(fl, orc, K, L, b, R, 7, 5)
     ocounts, oids = orc.build_tables(op, keys)
-    counts, ids = gpu_insert(fl, p, keys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
     q = 500
     wi, wc = orc.query(op, ocounts, oids, keys[:q], 40, self_ids=np.arange(q, dtype=np.int32))
-    gi, gc = gpu_query(fl, p, counts, ids, n, keys[:q], 40, np.arange(q, dtype=np.int32))
+    gi, gc = gpu_query(fl, p, index, n, keys[:q], 40, np.arange(q, dtype=np.int32))
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
 
 
@@ -969,12 +979,12 @@ def test_shared_pool_of_any_size(fl, orc, K, L, b, R, permille):
     LM = L << (K * b)
     assert P == max(1, -(-LM * permille // 1000))
     ocounts, oids = orc.build_tables(op, keys)
-    counts, ids = gpu_insert(fl, p, keys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 1, P, R)
     q = 2000
     k = min(64, L * R)
     wi, wc = orc.query(op, ocounts, oids, keys[:q], k, self_ids=np.arange(q, dtype=np.int32))
-    gi, gc = gpu_query(fl, p, counts, ids, n, keys[:q], k, np.arange(q, dtype=np.int32))
+    gi, gc = gpu_query(fl, p, index, n, keys[:q], k, np.arange(q, dtype=np.int32))
     assert np.array_equal(gi, wi) and np.array_equal(gc, wc)
 
 
@@ -988,13 +998,13 @@ def test_shared_url_graph_and_append(fl, orc):
     rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
     rp, ci = rp_d.cpu().numpy(), ci_d.cpu().numpy()
     p, op, P = _shared_pair(fl, orc, 5, 32, 3, 64, 1, 200)
-    counts, ids, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, 32)
+    index, oi, oc = _gpu_graph(fl, p, rp_d, ci_d, 32)
     okeys = orc.doph(op, rp, ci)
     ocounts, oids = orc.build_tables(op, okeys)
-    occupied_equal(u32(counts), i32(ids), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)
     n = spec.n_rows
     sample = np.arange(0, n, 41)
     wi, wc = orc.query(op, ocounts, oids, okeys[sample], 32, self_ids=sample.astype(np.int32))
     assert np.array_equal(i32(oi)[sample], wi) and np.array_equal(i32(oc)[sample], wc)
-    c2, i2 = _append_batches(fl, p, okeys, [0, 70_000, 70_001, 150_000, n], [2, 0, 3, 1])
-    occupied_equal(u32(c2), i32(i2), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)
+    index2 = _append_batches(fl, p, okeys, [0, 70_000, 70_001, 150_000, n], [2, 0, 3, 1])
+    occupied_equal(*host_index(fl, p, index2), ocounts.reshape(-1), oids.reshape(-1), 1, P, 64)

@@ -61,8 +61,11 @@ def test_param_checks_run_on_the_host(fl):
 
 def test_index_and_workspace_sizes(fl):
     p = fl.flash_params.make(4, 64, 4, 128)
-    ce, ie = fl.flash_index_elems(p)
-    assert ce == 64 * 65536 and ie == 64 * 65536 * 128
+    P, S, words = fl.flash_index_layout(p)
+    # header (count + 3 reserved words) and 128 slots, rounded up to 128 bytes
+    assert P == 64 * 65536 and S == 160 and words == P * S
+    for R, want in ((1, 32), (28, 32), (29, 64), (32, 64), (64, 96), (256, 288), (1024, 1056)):
+        assert fl.flash_index_layout(fl.flash_params.make(1, 8, 2, R))[1] == want, R
     n = 350_000
     ins = fl.flash_workspace_bytes(fl.OP_INSERT, p, n_rows=n)
     assert ins >= 8 * n * 64 + 8 * 64 * 65536
@@ -79,16 +82,21 @@ def test_device_calls_reject_bad_arguments_before_launch(fl):
     p = fl.flash_params.make(4, 16, 4, 32)
     rc = L.flash_hash(ctypes.byref(p), 10, 100, None, None, None, None, None)
     assert rc == fl.FLASH_EINVAL
-    rc = L.flash_insert_keys(ctypes.byref(p), 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
-                             ctypes.c_void_p(16), None, 0, None)
+    rc = L.flash_insert_keys(ctypes.byref(p), 10, ctypes.c_void_p(16), ctypes.c_void_p(16), None, 0, None)
     assert rc == fl.FLASH_ENOSPC
-    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), 10, 10,
+    # the index array must be 16-byte aligned (every task is one 16-byte load)
+    rc = L.flash_insert_keys(ctypes.byref(p), 10, ctypes.c_void_p(16), ctypes.c_void_p(20), None, 0, None)
+    assert rc == fl.FLASH_EINVAL and b"aligned" in L.flash_last_error()
+    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(24), 10, 10, ctypes.c_void_p(16), None, 8,
+                            ctypes.c_void_p(16), ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 20, None)
+    assert rc == fl.FLASH_EINVAL and b"aligned" in L.flash_last_error()
+    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), 10, 10,
                             ctypes.c_void_p(16), None, 0, ctypes.c_void_p(16), ctypes.c_void_p(16),
                             ctypes.c_void_p(16), 1 << 20, None)
     assert rc == fl.FLASH_EINVAL
     assert b"k must be" in L.flash_last_error()
     # query ids travel between table-size stages as 32-bit words
-    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), ctypes.c_void_p(16), 10, 1 << 31,
+    rc = L.flash_query_keys(ctypes.byref(p), ctypes.c_void_p(16), 10, 1 << 31,
                             ctypes.c_void_p(16), None, 10, ctypes.c_void_p(16), ctypes.c_void_p(16),
                             ctypes.c_void_p(16), 1 << 20, None)
     assert rc == fl.FLASH_ENOTIMPL
@@ -134,19 +142,19 @@ def test_append_arguments_are_checked_on_the_host(fl):
     L = fl.lib()
     for n, base in ((10, -1), (10, (1 << 31) - 5)):
         r = L.flash_insert_keys_append(ctypes.byref(p), n, ctypes.c_void_p(16), base, ctypes.c_void_p(16),
-                                       ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+                                       ctypes.c_void_p(16), 1 << 30, None)
         assert r == fl.FLASH_EINVAL
     # ids past what a query can hold in its packed (id, count) words: L = 16
     # leaves 27 id bits
     r = L.flash_insert_keys_append(ctypes.byref(p), 10, ctypes.c_void_p(16), (1 << 27) - 5, ctypes.c_void_p(16),
-                                   ctypes.c_void_p(16), ctypes.c_void_p(16), 1 << 30, None)
+                                   ctypes.c_void_p(16), 1 << 30, None)
     assert r == fl.FLASH_ENOTIMPL
     # too small a workspace
     r = L.flash_insert_keys_append(ctypes.byref(p), 1000, ctypes.c_void_p(16), 0, ctypes.c_void_p(16),
-                                   ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None)
+                                   ctypes.c_void_p(16), 8, None)
     assert r == fl.FLASH_ENOSPC
     # nothing to add: nothing enqueued, no workspace needed
-    assert L.flash_insert_keys_append(ctypes.byref(p), 0, None, 5, ctypes.c_void_p(16), ctypes.c_void_p(16),
+    assert L.flash_insert_keys_append(ctypes.byref(p), 0, None, 5, ctypes.c_void_p(16),
                                       None, 0, None) == fl.FLASH_OK
 
 
@@ -162,9 +170,9 @@ def test_shared_pool_size_matches_the_oracle(fl, orc):
     # the library's pool arithmetic against the oracle's (both read Sec. 3.5)
     for K, L, b, R, permille in ((4, 64, 4, 128, 200), (5, 32, 3, 64, 500), (2, 3, 3, 4, 1),
                                  (1, 2, 2, 8, 500), (4, 16, 4, 32, 999), (4, 16, 4, 32, 1000), (4, 16, 4, 32, 0)):
-        ce, ie = fl.flash_index_elems(fl.flash_params.make(K, L, b, R, share_permille=permille))
+        ce, S, words = fl.flash_index_layout(fl.flash_params.make(K, L, b, R, share_permille=permille))
         P = orc.pool_size(orc.params(K, L, b, R, share_permille=permille))
-        assert ce == P and ie == P * R, (K, L, b, permille)
+        assert ce == P and words == P * S, (K, L, b, permille)
 
 
 def test_noalloc_query_checks_its_fixed_scratch_on_the_host(fl):
@@ -176,11 +184,11 @@ def test_noalloc_query_checks_its_fixed_scratch_on_the_host(fl):
     p = fl.flash_params.make(4, 64, 4, 128)
     need = fl.flash_workspace_bytes(fl.OP_QUERY, p, n_queries=200_000, k=8)
     assert need > 32 << 20
-    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 200_000, 100, vp, vp, None, 8, vp, vp, None)
+    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, 10, 200_000, 100, vp, vp, None, 8, vp, vp, None)
     assert r == fl.FLASH_ENOSPC
     assert b"scratch" in L.flash_last_error()
-    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 10, 100, vp, vp, None, 0, vp, vp, None)
+    r = L.flash_query_batch_noalloc(ctypes.byref(p), vp, 10, 10, 100, vp, vp, None, 0, vp, vp, None)
     assert r == fl.FLASH_EINVAL
     # nothing to answer: nothing enqueued
-    assert L.flash_query_batch_noalloc(ctypes.byref(p), vp, vp, 10, 0, 0, vp, None, None, 8, vp, vp,
+    assert L.flash_query_batch_noalloc(ctypes.byref(p), vp, 10, 0, 0, vp, None, None, 8, vp, vp,
                                        None) == fl.FLASH_OK

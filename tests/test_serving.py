@@ -148,9 +148,9 @@ def test_gpu_continuous_serving_equals_alone(orc):
     spec = datagen.URL
     rp_d, ci_d = datagen.make_rows(spec, 1, device="cuda")
     p = flash.flash_params.make(5, 32, 3, 64, seed=1)
-    counts, ids = flash.alloc_index(p)
+    index = flash.alloc_index(p)
     ws = flash.alloc_workspace(flash.OP_BUILD, p, n_rows=spec.n_rows)
-    flash.flash_build_index(p, rp_d, ci_d, counts, ids, ws)
+    flash.flash_build_index(p, rp_d, ci_d, index, ws)
     torch.cuda.synchronize()
     rp, ci = rp_d.cpu(), ci_d.cpu()
     del ws, rp_d, ci_d
@@ -168,7 +168,7 @@ def test_gpu_continuous_serving_equals_alone(orc):
         return (qrp[st:st + n + 1] - a).astype(np.int64), qci[a:b].copy()
     reqs = serving.make_requests(rows, 240, qps=2e6, seed=11, max_batch=4096)
     assert {r.k for r in reqs} == {10, 50, 200}
-    ex = serving.GpuExecutor(p, counts, ids, spec.n_rows)
+    ex = serving.GpuExecutor(p, index, spec.n_rows)
     stats = serving.ContinuousServer(ex, budget_bytes=1 << 30, slots=8).run(reqs)
     assert stats["requests"] == 240 and stats["rejected"] == 0
     # each result is the same as the request run alone, and as the oracle
