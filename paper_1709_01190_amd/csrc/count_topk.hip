@@ -885,8 +885,10 @@ __host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
 // bit is its top 15 bits (word = top 10), the suspect table slot its top 8,
 // and the suspects' filter bit its top 13 (word = the slot, so one address
 // reaches both).  An id that shares a suspect's top bits costs at most a
-// longer probe; results never depend on the hash.
-__device__ __forceinline__ uint32_t id_hash(uint32_t id) { return id * 0x9E3779B1u; }
+// longer probe; results never depend on the hash.  The multiply takes the
+// id's low 24 bits (a full-rate 24-bit multiply instead of a quarter-rate
+// 32-bit one): ids 2^24 apart share a hash, which costs the same.
+__device__ __forceinline__ uint32_t id_hash(uint32_t id) { return __umul24(id, 0x3779B1u); }
 __device__ __forceinline__ uint32_t ts_slot_of(uint32_t h) { return h >> 24; }
 
 // Bins [0, 512): lane l holds bins 8l .. 8l+7.  Returns the bin b* where the
