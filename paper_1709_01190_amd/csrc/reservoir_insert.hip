@@ -49,6 +49,7 @@ __global__ void fill_strided_u32_kernel(uint32_t* p, uint64_t n, uint32_t stride
 
 constexpr uint32_t kChunk = 16384;  // buckets per LDS histogram (64 KiB)
 constexpr int kPartThreads = 512;
+constexpr int kPartUnroll = 4;
 
 // With shared reservoirs each key is replaced by its reservoir (keys >= M,
 // the empty key included, stay empty).
@@ -153,13 +154,24 @@ __global__ __launch_bounds__(kPartThreads) void part_count_kernel(PartArgs a) {
   const uint32_t v0 = sl * a.slice_vecs;
   uint32_t v1 = v0 + a.slice_vecs;
   if (v1 > a.np / 4) v1 = a.np / 4;
-  for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
-    const uint4 x = rowv[v];
-    const uint32_t d0 = x.x - lo, d1 = x.y - lo, d2 = x.z - lo, d3 = x.w - lo;
-    if (d0 < cl) atomicAdd(&h[d0], 1u);
-    if (d1 < cl) atomicAdd(&h[d1], 1u);
-    if (d2 < cl) atomicAdd(&h[d2], 1u);
-    if (d3 < cl) atomicAdd(&h[d3], 1u);
+  // kPartUnroll 16-byte loads per thread are in flight before their keys are
+  // counted (one workgroup per CU: the loads' latency is hidden by the
+  // thread's own later loads, not by other waves)
+  for (uint32_t vb = v0 + threadIdx.x; vb < v1; vb += kPartUnroll * kPartThreads) {
+    uint4 x[kPartUnroll];
+#pragma unroll
+    for (int u = 0; u < kPartUnroll; ++u) {
+      const uint32_t v = vb + (uint32_t)u * kPartThreads;
+      x[u] = v < v1 ? rowv[v] : make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    }
+#pragma unroll
+    for (int u = 0; u < kPartUnroll; ++u) {
+      const uint32_t d0 = x[u].x - lo, d1 = x[u].y - lo, d2 = x[u].z - lo, d3 = x[u].w - lo;
+      if (d0 < cl) atomicAdd(&h[d0], 1u);
+      if (d1 < cl) atomicAdd(&h[d1], 1u);
+      if (d2 < cl) atomicAdd(&h[d2], 1u);
+      if (d3 < cl) atomicAdd(&h[d3], 1u);
+    }
   }
   __syncthreads();
   const uint64_t b0 = (uint64_t)t * a.M + lo;
@@ -185,14 +197,23 @@ __global__ __launch_bounds__(kPartThreads) void part_scatter_kernel(PartArgs a) 
   const uint32_t v0 = sl * a.slice_vecs;
   uint32_t v1 = v0 + a.slice_vecs;
   if (v1 > a.np / 4) v1 = a.np / 4;
-  for (uint32_t v = v0 + threadIdx.x; v < v1; v += kPartThreads) {
-    const uint4 x = rowv[v];
-    const uint32_t kk[4] = {x.x, x.y, x.z, x.w};
-    const uint32_t row0 = a.row_mod ? (4 * v) % a.row_mod : 4 * v;  // row_mod is a multiple of 64
+  for (uint32_t vb = v0 + threadIdx.x; vb < v1; vb += kPartUnroll * kPartThreads) {
+    uint4 x[kPartUnroll];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t d = kk[j] - lo;
-      if (d < cl) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + row0 + (uint32_t)j);
+    for (int u = 0; u < kPartUnroll; ++u) {
+      const uint32_t v = vb + (uint32_t)u * kPartThreads;
+      x[u] = v < v1 ? rowv[v] : make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    }
+#pragma unroll
+    for (int u = 0; u < kPartUnroll; ++u) {
+      const uint32_t v = vb + (uint32_t)u * kPartThreads;
+      const uint32_t kk[4] = {x[u].x, x[u].y, x[u].z, x[u].w};
+      const uint32_t row0 = a.row_mod ? (4 * v) % a.row_mod : 4 * v;  // row_mod is a multiple of 64
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t d = kk[j] - lo;
+        if (d < cl) a.staged[atomicAdd(&cur[d], 1u)] = (int32_t)(a.id_base + row0 + (uint32_t)j);
+      }
     }
   }
 }
@@ -385,10 +406,19 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
   if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, occ);
   if (n >= 1 && n <= (uint32_t)kSmall) {
     const uint32_t t = (uint32_t)(bk / a.M);
+    uint32_t idc[kSmall];
+    if (!a.append) {
+      // the candidates are one run of `staged`: every load is issued before
+      // any is used (past the run's end the last one is read again)
+#pragma unroll
+      for (int i = 0; i < kSmall; ++i) idc[i] = (uint32_t)a.staged[start + ((uint32_t)i < n ? (uint32_t)i : n - 1)];
+    } else {
+#pragma unroll
+      for (int i = 0; i < kSmall; ++i) idc[i] = (uint32_t)i < n ? candidate(a, bk, start, occ, (uint32_t)i) : 0u;
+    }
     uint64_t pk[kSmall];
 #pragma unroll
-    for (int i = 0; i < kSmall; ++i)
-      pk[i] = (uint32_t)i < n ? priority(a.s_p, t, candidate(a, bk, start, occ, (uint32_t)i)) : ~0ull;
+    for (int i = 0; i < kSmall; ++i) pk[i] = (uint32_t)i < n ? priority(a.s_p, t, idc[i]) : ~0ull;
 #pragma unroll
     for (int i = 0; i < kSmall; ++i) {
       if ((uint32_t)i >= n) break;
