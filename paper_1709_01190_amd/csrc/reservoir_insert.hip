@@ -18,6 +18,8 @@
 //               - buckets of <= 8 arrivals: one thread, ranks in registers
 //               - 9..64 arrivals: the wave of the bucket's thread, one arrival
 //                 per lane, a bitonic sort across the lanes in registers
+//               - 65..256 arrivals: one wave per bucket, two or four arrivals
+//                 per lane, a bitonic sort in registers (no LDS)
 //               - larger buckets: one wave; all arrivals sorted in LDS when few,
 //                 else a priority threshold keeps ~2R candidates (bisected until
 //                 between R and the LDS capacity), which are then sorted.
@@ -305,7 +307,8 @@ struct SelectArgs {
   const int32_t* staged;
   uint4* work;          // [nb] {bucket, first staged slot, candidates, old slots}
                         // of the large buckets, from the back
-  uint32_t* wl_len;     // [2] [1]: large buckets listed ([0] unused)
+  uint32_t* wl_len;     // [2] buckets listed: [0] mid-size (from the front of
+                        // `work`), [1] large (from the back)
   uint64_t n_buckets;
   uint64_t s_p;
   uint32_t M;
@@ -320,7 +323,8 @@ __device__ __forceinline__ uint32_t candidate(const SelectArgs& a, uint64_t bk, 
   return i < occ ? (uint32_t)a.index[bk * (uint64_t)a.S + kSlot0 + i] : (uint32_t)a.staged[start + i - occ];
 }
 
-constexpr uint32_t kMid = 64;  // arrivals handled by one wave in registers
+constexpr uint32_t kMid = 64;   // arrivals handled by one wave in registers, one per lane
+constexpr uint32_t kRegMax = 256;  // arrivals sorted in registers, up to four per lane
 
 // Appends for the lanes where pred holds, with one atomic per wave; returns
 // each such lane's slot.
@@ -401,7 +405,10 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
   const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
   const uint32_t start = in ? a.seg[bk] : 0u;
   if (in) a.index[bk * (uint64_t)a.S] = (int32_t)(old + nn);
-  const bool big = n > kMid;
+  const bool mid = n > kMid && n <= kRegMax;
+  const bool big = n > kRegMax;
+  const uint32_t pm = wave_append(&a.wl_len[0], mid);
+  if (mid) a.work[pm] = make_uint4((uint32_t)bk, start, n, occ);
   const uint32_t pb = wave_append(&a.wl_len[1], big);
   if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, occ);
   if (n >= 1 && n <= (uint32_t)kSmall) {
@@ -435,7 +442,93 @@ __global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) 
   sort_buckets_by_segments<64>(a, bk, n, start, occ, 32u);
 }
 
-// One wave per large bucket (n > 64).
+// Ascending bitonic sort of the wave's 64 * KPL values, element e = lane * KPL
+// + i in v[i] of lane `lane`: exchanges with a partner element e ^ j inside
+// the lane when j < KPL, else with the same register of lane (lane ^ j / KPL).
+template <int KPL>
+__device__ __forceinline__ void wave_sort_u64(uint64_t (&v)[KPL]) {
+  const uint32_t lane = threadIdx.x & 63;
+  constexpr uint32_t N = 64u * KPL;
+#pragma unroll
+  for (uint32_t k = 2; k <= N; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j >= (uint32_t)KPL) {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+          const uint32_t e = lane * KPL + (uint32_t)i;
+          const uint64_t o = xor_lane64(v[i], j / KPL);
+          const uint64_t mn = v[i] < o ? v[i] : o, mx = v[i] < o ? o : v[i];
+          v[i] = (((e & j) == 0) == ((e & k) == 0)) ? mn : mx;
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < KPL; ++i) {
+          if ((i & (int)j) == 0) {
+            const int i2 = i | (int)j;
+            const bool asc = ((lane * KPL + (uint32_t)i) & k) == 0;
+            const uint64_t x = v[i], y = v[i2];
+            const bool sw = asc ? (x > y) : (x < y);
+            v[i] = sw ? y : x;
+            v[i2] = sw ? x : y;
+          }
+        }
+      }
+    }
+  }
+}
+
+// One bucket with kMid < n <= 64 * KPL candidates: all in registers, sorted,
+// the first min(n, R) written.
+template <int KPL>
+__device__ __forceinline__ void select_in_registers(const SelectArgs& a, uint32_t bk, uint32_t start, uint32_t n,
+                                                    uint32_t occ) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t t = bk / a.M;
+  uint32_t idc[KPL];
+  if (!a.append) {
+    // one run of `staged`: all loads issued together (past its end the last
+    // candidate is read again)
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+      const uint32_t e = lane * KPL + (uint32_t)i;
+      idc[i] = (uint32_t)a.staged[start + (e < n ? e : n - 1)];
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < KPL; ++i) {
+      const uint32_t e = lane * KPL + (uint32_t)i;
+      idc[i] = e < n ? candidate(a, bk, start, occ, e) : 0u;
+    }
+  }
+  uint64_t v[KPL];
+#pragma unroll
+  for (int i = 0; i < KPL; ++i) v[i] = lane * KPL + (uint32_t)i < n ? priority(a.s_p, t, idc[i]) : ~0ull;
+  wave_sort_u64<KPL>(v);
+  // every candidate was read above: the reservoir can be overwritten
+  const uint32_t keep = n < (uint32_t)a.R ? n : (uint32_t)a.R;
+  int32_t* slots = a.index + (uint64_t)bk * a.S + kSlot0;
+#pragma unroll
+  for (int i = 0; i < KPL; ++i) {
+    const uint32_t e = lane * KPL + (uint32_t)i;
+    if (e < keep) slots[e] = (int32_t)(uint32_t)v[i];
+  }
+}
+
+// One wave per mid-size bucket (kMid < n <= kRegMax), no LDS, so the CUs keep
+// as many waves as their registers allow.
+__global__ __launch_bounds__(64) void bucket_select_mid_kernel(SelectArgs a) {
+  const uint32_t len = a.wl_len[0];
+  for (uint32_t w = blockIdx.x; w < len; w += gridDim.x) {
+    const uint4 e = a.work[w];
+    if (e.z <= 128u)
+      select_in_registers<2>(a, e.x, e.y, e.z, e.w);
+    else
+      select_in_registers<4>(a, e.x, e.y, e.z, e.w);
+  }
+}
+
+// One wave per large bucket (n > kRegMax).
 __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
   __shared__ uint64_t buf[kWaveCap];
   __shared__ uint32_t cnt_sh;
@@ -642,6 +735,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   a.R = c.R;
   a.append = append ? 1 : 0;
   hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(bucket_select_mid_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   return hipGetLastError();
 }
