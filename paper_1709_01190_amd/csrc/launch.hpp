@@ -59,8 +59,12 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
 struct InsertWs {
   uint32_t* keys_t;     // [L][np]        table-major keys (rows padded to 64)
   int32_t* staged;      // [n_rows * L]   row ids grouped by bucket
-  uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)
+  uint32_t* part;       // [L * M * S]    arrivals per (bucket, row slice)       (one-level partition)
   uint32_t* partoff;    // [L * M * S]    exclusive prefix of part
+  uint32_t* ent;        // [L][tiles][8192] tile entries sorted by chunk           (two-level partition)
+  uint32_t* tile_off;   // [L][tiles][chunks + 1] chunk offsets in each tile
+  uint32_t* chunk_tot;  // [L * chunks]   arrivals per chunk
+  uint32_t* chunk_base; // [L * chunks]   their first staged slot
   uint32_t* seg;        // [L * M]        first staged slot of each bucket
   uint32_t* newcnt;     // [L * M]        the batch's arrivals per bucket
   uint4* work;          // [L * M]        {bucket, start, size} of the large buckets

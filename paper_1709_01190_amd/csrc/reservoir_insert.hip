@@ -298,6 +298,196 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
   }
 }
 
+// ---- two-level partition (buckets that receive few arrivals each)
+//   tile    : block (t, tile of kTileE entries of keys_t[t]) counting-sorts
+//             its entries by chunk of CH buckets in LDS and writes them back
+//             in that order (contiguous writes), with each chunk's offsets
+//             in the tile and its count added to the chunk's total
+//   scan    : chunk_base = exclusive prefix of the chunk totals (table-major)
+//   chunk   : block (t, chunk) reads the chunk's run of every tile, histograms
+//             it by bucket in LDS, writes newcnt and seg of its CH buckets,
+//             then places each row id in the chunk's region of `staged`,
+//             which is small enough for its partial lines to merge in L2
+// It produces the same newcnt, seg and (up to the order inside a bucket's
+// run) staged as the one-level partition.
+constexpr uint32_t kTileE = 8192;        // entries per tile (13 bits of row offset)
+constexpr uint32_t kMaxChunks2 = 256;    // chunks per table (one scan value per thread)
+constexpr uint32_t kMaxCh2 = 4096;       // buckets per chunk (LDS histogram)
+
+struct TwoArgs {
+  const uint32_t* keys_t;   // [Lp][np_part]
+  uint32_t* ent;            // [Lp][n_tiles][kTileE] entries (row offset << chb | bucket in chunk)
+  uint32_t* tile_off;       // [Lp][n_tiles][n_chunks + 1] chunk offsets inside each tile
+  uint32_t* chunk_tot;      // [Lp * n_chunks] arrivals per chunk (zeroed before the tile kernel)
+  const uint32_t* chunk_base;  // [Lp * n_chunks] their first staged slot
+  uint32_t* newcnt;
+  uint32_t* seg;
+  int32_t* staged;
+  uint32_t np, M;           // row length and buckets of the partition
+  uint32_t chb, n_chunks, n_tiles;
+  uint32_t id_base, row_mod;
+  uint32_t out_cap;         // ids a chunk may assemble in LDS
+};
+
+__global__ __launch_bounds__(256) void tile_partition_kernel(TwoArgs a) {
+  extern __shared__ uint32_t sm2[];
+  __shared__ uint32_t sh[4];
+  uint32_t* cnt = sm2;                     // [n_chunks + 1] counts, then offsets
+  uint32_t* ent = sm2 + kMaxChunks2 + 4;   // [kTileE]
+  const uint32_t tile = blockIdx.x, t = blockIdx.y;
+  const uint32_t ch = 1u << a.chb;
+  for (uint32_t c = threadIdx.x; c <= a.n_chunks; c += 256) cnt[c] = 0;
+  __syncthreads();
+  constexpr int kPer = kTileE / 256 / 4;   // 16-byte loads per thread
+  const uint32_t e0 = tile * kTileE;
+  const uint4* rowv = reinterpret_cast<const uint4*>(a.keys_t + (uint64_t)t * a.np);
+  uint32_t key[4 * kPer], rk[4 * kPer];
+#pragma unroll
+  for (int u = 0; u < kPer; ++u) {
+    const uint32_t v = e0 / 4 + threadIdx.x + (uint32_t)u * 256;
+    const uint4 x = 4 * v < a.np ? rowv[v] : make_uint4(kEmpty, kEmpty, kEmpty, kEmpty);
+    key[4 * u] = x.x;
+    key[4 * u + 1] = x.y;
+    key[4 * u + 2] = x.z;
+    key[4 * u + 3] = x.w;
+  }
+#pragma unroll
+  for (int j = 0; j < 4 * kPer; ++j) {
+    rk[j] = 0;
+    if (key[j] < a.M) rk[j] = atomicAdd(&cnt[key[j] >> a.chb], 1u);
+  }
+  __syncthreads();
+  const uint32_t my = threadIdx.x < a.n_chunks ? cnt[threadIdx.x] : 0u;
+  uint32_t total;
+  const uint32_t off = block_excl_scan(my, &total, sh);
+  uint32_t* toff = a.tile_off + ((uint64_t)t * a.n_tiles + tile) * (a.n_chunks + 1);
+  if (threadIdx.x < a.n_chunks) {
+    cnt[threadIdx.x] = off;
+    toff[threadIdx.x] = off;
+    if (my) atomicAdd(&a.chunk_tot[(uint64_t)t * a.n_chunks + threadIdx.x], my);
+  }
+  if (threadIdx.x == 0) toff[a.n_chunks] = total;
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 4 * kPer; ++j) {
+    if (key[j] < a.M) {
+      const uint32_t e = 4 * (threadIdx.x + (uint32_t)(j / 4) * 256) + (uint32_t)(j % 4);  // offset in the tile
+      ent[cnt[key[j] >> a.chb] + rk[j]] = (e << a.chb) | (key[j] & (ch - 1));
+    }
+  }
+  __syncthreads();
+  uint32_t* out = a.ent + ((uint64_t)t * a.n_tiles + tile) * kTileE;
+  for (uint32_t i = threadIdx.x; i < total; i += 256) out[i] = ent[i];
+}
+
+constexpr uint32_t kTB = 512;   // tiles whose run bounds sit in LDS at a time
+
+__global__ __launch_bounds__(256) void chunk_scatter_kernel(TwoArgs a) {
+  // [ch] counts, then cursors; [2 * kTB] run bounds; [out_cap] the chunk's
+  // region of `staged`, assembled before it is written
+  extern __shared__ uint32_t hc[];
+  __shared__ uint32_t sh[4];
+  const uint32_t c = blockIdx.x, t = blockIdx.y;
+  const uint32_t ch = 1u << a.chb, lo = c * ch;
+  const uint32_t cl = a.M - lo < ch ? a.M - lo : ch;
+  const uint32_t lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t* tb = hc + ch;
+  for (uint32_t j = threadIdx.x; j < ch; j += 256) hc[j] = 0;
+  const uint64_t tb0 = (uint64_t)t * a.n_tiles;
+  // Calls fn(entry, tile) for every entry of the chunk's run in every tile.
+  // The run bounds of kTB tiles are loaded into LDS at once; a wave takes
+  // four tiles per step and has the loads of all four (two entries per lane
+  // each) in flight before using any.
+  auto for_each_entry = [&](auto&& fn) {
+    for (uint32_t g0 = 0; g0 < a.n_tiles; g0 += kTB) {
+      const uint32_t gn = a.n_tiles - g0 < kTB ? a.n_tiles - g0 : kTB;
+      __syncthreads();
+      for (uint32_t i = threadIdx.x; i < gn; i += 256) {
+        const uint32_t* toff = a.tile_off + (tb0 + g0 + i) * (a.n_chunks + 1) + c;
+        tb[2 * i] = toff[0];
+        tb[2 * i + 1] = toff[1];
+      }
+      __syncthreads();
+      for (uint32_t i0 = wv; i0 < gn; i0 += 16) {
+        uint32_t x[8];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t i = i0 + 4u * (uint32_t)u;
+          const uint32_t b0 = i < gn ? tb[2 * i] : 0u, b1 = i < gn ? tb[2 * i + 1] : 0u;
+          const uint32_t* run = a.ent + (tb0 + g0 + i) * kTileE;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const uint32_t j = b0 + 64u * (uint32_t)h + lane;
+            x[2 * u + h] = j < b1 ? run[j] : kEmpty;
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            if (x[2 * u + h] != kEmpty) fn(x[2 * u + h], g0 + i0 + 4u * (uint32_t)u);
+        // runs longer than 128 entries
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const uint32_t i = i0 + 4u * (uint32_t)u;
+          if (i < gn) {
+            const uint32_t b0 = tb[2 * i], b1 = tb[2 * i + 1];
+            const uint32_t* run = a.ent + (tb0 + g0 + i) * kTileE;
+            for (uint32_t j = b0 + 128 + lane; j < b1; j += 64) fn(run[j], g0 + i);
+          }
+        }
+      }
+    }
+  };
+  // 1. histogram of the chunk's buckets
+  for_each_entry([&](uint32_t x, uint32_t) { atomicAdd(&hc[x & (ch - 1)], 1u); });
+  __syncthreads();
+  // 2. counts and first slots of the chunk's buckets; the counts become cursors
+  constexpr uint32_t kPer = kMaxCh2 / 256;
+  uint32_t v[kPer];
+  uint32_t sum = 0;
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t j = threadIdx.x * kPer + i;
+    v[i] = j < cl ? hc[j] : 0u;
+    sum += v[i];
+  }
+  uint32_t total;
+  uint32_t run_off = block_excl_scan(sum, &total, sh);
+  const uint32_t base = a.chunk_base[(uint64_t)t * a.n_chunks + c];
+  const uint64_t b0 = (uint64_t)t * a.M + lo;
+  __syncthreads();
+#pragma unroll
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t j = threadIdx.x * kPer + i;
+    if (j < cl) {
+      a.newcnt[b0 + j] = v[i];
+      a.seg[b0 + j] = base + run_off;
+      hc[j] = run_off;
+    }
+    run_off += v[i];
+  }
+  // 3. each arrival's row id at its bucket's cursor (the bounds are loaded
+  // again behind a barrier inside for_each_entry): into LDS and then out with
+  // contiguous stores, or straight to `staged` when the chunk holds more than
+  // the LDS region
+  uint32_t* outb = tb + 2 * kTB;
+  const bool in_lds = total <= a.out_cap;
+  for_each_entry([&](uint32_t x, uint32_t tile) {
+    const uint32_t e = tile * kTileE + (x >> a.chb);
+    const uint32_t row = a.row_mod ? e % a.row_mod : e;
+    const uint32_t pos = atomicAdd(&hc[x & (ch - 1)], 1u);
+    if (in_lds)
+      outb[pos] = a.id_base + row;
+    else
+      a.staged[base + pos] = (int32_t)(a.id_base + row);
+  });
+  if (in_lds) {
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < total; i += 256) a.staged[base + i] = (int32_t)outb[i];
+  }
+}
+
 struct SelectArgs {
   int32_t* index;          // reservoir b: count at index[b * S] (in when appending, and out),
                            // slot i at index[b * S + kSlot0 + i]
@@ -620,6 +810,10 @@ struct Geo {
   uint64_t Mp;                 // partition buckets per table
   uint32_t ch, n_chunks, n_slices, slice_vecs;
   uint64_t nb, nparts, tiles;
+  // two-level partition (two_level): chunks of 2^chb buckets, tiles of kTileE entries
+  bool two_level;
+  uint32_t chb, n_chunks2, n_tiles2;
+  uint64_t tiles2;              // scan tiles over the Lp * n_chunks2 chunk totals
 };
 
 Geo geometry(const Cfg& c, int64_t n_rows) {
@@ -643,7 +837,31 @@ Geo geometry(const Cfg& c, int64_t n_rows) {
   g.nb = (uint64_t)g.Lp * g.Mp;
   g.nparts = g.nb * s;
   g.tiles = (g.nparts + kTile - 1) / kTile;
+  // Two-level partition when the buckets receive few arrivals: chunks of
+  // at least Mp / 64 buckets (runs of ~128 entries per tile), halved down
+  // to Mp / 256 while a chunk's region of `staged` exceeds 64 KiB; taken
+  // if that region is at most 128 KiB and the histogram fits LDS.
+  const double per_bucket = (double)g.np_part / (double)g.Mp;
+  uint32_t chb = 6;
+  while ((1ull << chb) * 64 < g.Mp) ++chb;
+  while (chb > 6 && (double)(1ull << chb) * per_bucket * 4.0 > 65536.0 && (1ull << (chb - 1)) * kMaxChunks2 >= g.Mp)
+    --chb;
+  g.chb = chb;
+  g.n_chunks2 = (uint32_t)((g.Mp + (1ull << chb) - 1) >> chb);
+  g.n_tiles2 = (g.np_part + kTileE - 1) / kTileE;
+  g.two_level = (1u << chb) <= kMaxCh2 && g.n_chunks2 <= kMaxChunks2 &&
+                (double)(1ull << chb) * per_bucket * 4.0 <= 131072.0 && g.Mp < (1ull << 31);
+  g.tiles2 = ((uint64_t)g.Lp * g.n_chunks2 + kTile - 1) / kTile;
   return g;
+}
+
+// Bytes of the partition's own buffers: part and partoff (one level), or the
+// entries, tile offsets, chunk totals and chunk bases (two levels).
+uint64_t part_bytes(const Geo& g) {
+  if (!g.two_level) return 2 * align256(4 * g.nparts);
+  const uint64_t chunks = (uint64_t)g.Lp * g.n_chunks2;
+  return align256(4ull * g.Lp * g.n_tiles2 * kTileE) + align256(4ull * g.Lp * g.n_tiles2 * (g.n_chunks2 + 1)) +
+         2 * align256(4 * chunks);
 }
 
 }  // namespace
@@ -651,8 +869,9 @@ Geo geometry(const Cfg& c, int64_t n_rows) {
 size_t insert_ws_bytes(const Cfg& c, int64_t n_rows) {
   const Geo g = geometry(c, n_rows);
   const uint64_t ne = (uint64_t)(n_rows > 0 ? n_rows : 1) * c.L;
-  return align256(4 * (uint64_t)c.L * g.np) + align256(4 * ne) + 2 * align256(4 * g.nparts) +
-         2 * align256(4 * g.nb) + align256(16 * g.nb) + align256(4 * (g.tiles + 1)) + align256(8);
+  const uint64_t tiles = g.two_level ? g.tiles2 : g.tiles;
+  return align256(4 * (uint64_t)c.L * g.np) + align256(4 * ne) + part_bytes(g) +
+         2 * align256(4 * g.nb) + align256(16 * g.nb) + align256(4 * (tiles + 1)) + align256(8);
 }
 
 InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
@@ -664,10 +883,24 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
   p += align256(4 * (uint64_t)c.L * g.np);
   w.staged = (int32_t*)p;
   p += align256(4 * ne);
-  w.part = (uint32_t*)p;
-  p += align256(4 * g.nparts);
-  w.partoff = (uint32_t*)p;
-  p += align256(4 * g.nparts);
+  if (g.two_level) {
+    const uint64_t chunks = (uint64_t)g.Lp * g.n_chunks2;
+    w.part = w.partoff = nullptr;
+    w.ent = (uint32_t*)p;
+    p += align256(4ull * g.Lp * g.n_tiles2 * kTileE);
+    w.tile_off = (uint32_t*)p;
+    p += align256(4ull * g.Lp * g.n_tiles2 * (g.n_chunks2 + 1));
+    w.chunk_tot = (uint32_t*)p;
+    p += align256(4 * chunks);
+    w.chunk_base = (uint32_t*)p;
+    p += align256(4 * chunks);
+  } else {
+    w.ent = w.tile_off = w.chunk_tot = w.chunk_base = nullptr;
+    w.part = (uint32_t*)p;
+    p += align256(4 * g.nparts);
+    w.partoff = (uint32_t*)p;
+    p += align256(4 * g.nparts);
+  }
   w.seg = (uint32_t*)p;
   p += align256(4 * g.nb);
   w.newcnt = (uint32_t*)p;
@@ -675,7 +908,7 @@ InsertWs insert_ws_carve(const Cfg& c, int64_t n_rows, void* ws) {
   w.work = (uint4*)p;
   p += align256(16 * g.nb);
   w.tile_sums = (uint32_t*)p;
-  p += align256(4 * (g.tiles + 1));
+  p += align256(4 * ((g.two_level ? g.tiles2 : g.tiles) + 1));
   w.wl_len = (uint32_t*)p;
   return w;
 }
@@ -695,6 +928,46 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   sm.P = c.P;
   hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
                      (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t, sm);
+  if (g.two_level) {
+    const uint64_t chunks = (uint64_t)g.Lp * g.n_chunks2;
+    if ((e = launch_fill_u32(w.chunk_tot, chunks, 0u, s)) != hipSuccess) return e;
+    TwoArgs ta;
+    ta.keys_t = w.keys_t;
+    ta.ent = w.ent;
+    ta.tile_off = w.tile_off;
+    ta.chunk_tot = w.chunk_tot;
+    ta.chunk_base = w.chunk_base;
+    ta.newcnt = w.newcnt;
+    ta.seg = w.seg;
+    ta.staged = w.staged;
+    ta.np = g.np_part;
+    ta.M = (uint32_t)g.Mp;
+    ta.chb = g.chb;
+    ta.n_chunks = g.n_chunks2;
+    ta.n_tiles = g.n_tiles2;
+    ta.id_base = id_base;
+    ta.row_mod = c.shared ? g.np : 0u;
+    const size_t lds_tile = sizeof(uint32_t) * (kMaxChunks2 + 4 + kTileE);
+    hipLaunchKernelGGL(tile_partition_kernel, dim3(g.n_tiles2, g.Lp), dim3(256), lds_tile, s, ta);
+    const uint32_t tiles2 = (uint32_t)g.tiles2;
+    hipLaunchKernelGGL(scan_tile_sums_kernel, dim3(tiles2), dim3(kScanThreads), 0, s, w.chunk_tot, chunks,
+                       w.tile_sums);
+    hipLaunchKernelGGL(scan_tile_offsets_kernel, dim3(1), dim3(kScanThreads), 0, s, w.tile_sums, tiles2);
+    hipLaunchKernelGGL(scan_tiles_kernel, dim3(tiles2), dim3(kScanThreads), 0, s, w.chunk_tot, chunks,
+                       w.tile_sums, w.chunk_base);
+    // LDS for 1.25 times a chunk's expected arrivals, rounded up to a power
+    // of two, if that is at most 8K ids (32 KiB: four blocks per CU); larger
+    // chunks store straight to `staged`, which measured faster than two
+    // blocks per CU
+    const double per_chunk = (double)(1u << g.chb) * (double)g.np_part / (double)g.Mp;
+    uint32_t cap = 1024;
+    while (cap <= 8192 && (double)cap < 1.25 * per_chunk) cap <<= 1;
+    if (cap > 8192) cap = 0;
+    ta.out_cap = cap;
+    const size_t lds_chunk = sizeof(uint32_t) * ((1u << g.chb) + 2 * kTB + cap);
+    if ((e = allow_lds(reinterpret_cast<const void*>(&chunk_scatter_kernel), lds_chunk)) != hipSuccess) return e;
+    hipLaunchKernelGGL(chunk_scatter_kernel, dim3(g.n_chunks2, g.Lp), dim3(256), lds_chunk, s, ta);
+  } else {
   PartArgs pa;
   pa.keys_t = w.keys_t;
   pa.part = w.part;
@@ -721,6 +994,7 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   hipLaunchKernelGGL(bucket_totals_kernel, dim3(grid_for(g.nb, 256, 16)), dim3(256), 0, s, w.part,
                      w.partoff, g.nb, g.n_slices, w.newcnt, w.seg);
   hipLaunchKernelGGL(part_scatter_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
+  }
   SelectArgs a;
   a.index = index;
   a.S = c.S;
