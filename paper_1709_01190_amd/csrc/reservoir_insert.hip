@@ -298,6 +298,161 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
   }
 }
 
+struct SelectArgs {
+  int32_t* index;          // reservoir b: count at index[b * S] (in when appending, and out),
+                           // slot i at index[b * S + kSlot0 + i]
+  uint32_t S;
+  const uint32_t* newcnt;  // the batch's arrivals per bucket
+  const uint32_t* seg;     // their first staged slot
+  const int32_t* staged;
+  uint4* work;          // [nb] {bucket, first staged slot, candidates, old slots}
+                        // of the large buckets, from the back
+  uint32_t* wl_len;     // [2] buckets listed: [0] mid-size (from the front of
+                        // `work`), [1] large (from the back)
+  uint64_t n_buckets;
+  uint64_t s_p;
+  uint32_t M;
+  int R;
+  int append;           // 1: merge with the reservoirs already in the index
+};
+
+// Candidate i of bucket bk: its first `occ` are the ids already in the
+// reservoir (appending), the rest the batch's arrivals.
+__device__ __forceinline__ uint32_t candidate(const SelectArgs& a, uint64_t bk, uint32_t start, uint32_t occ,
+                                              uint32_t i) {
+  return i < occ ? (uint32_t)a.index[bk * (uint64_t)a.S + kSlot0 + i] : (uint32_t)a.staged[start + i - occ];
+}
+
+constexpr uint32_t kMid = 64;   // arrivals handled by one wave in registers, one per lane
+constexpr uint32_t kRegMax = 256;  // arrivals sorted in registers, up to four per lane
+
+// Appends for the lanes where pred holds, with one atomic per wave; returns
+// each such lane's slot.
+__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
+  const uint64_t m = __ballot(pred);
+  if (m == 0) return 0;
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
+  uint32_t base = 0;
+  if ((threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
+  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
+  return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Ascending sort of one 64-bit value per lane within each aligned segment of
+// SEG lanes (SEG a power of two <= 64), all segments at once.
+template <uint32_t SEG>
+__device__ __forceinline__ uint64_t segment_bitonic_sort(uint64_t v) {
+  const uint32_t lane = threadIdx.x & 63;
+#pragma unroll
+  for (uint32_t k = 2; k <= SEG; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t o = xor_lane64(v, j);
+      const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
+      const bool up = k == SEG || (lane & k) == 0;
+      v = (((lane & j) == 0) == up) ? mn : mx;
+    }
+  }
+  return v;
+}
+
+// The wave sorts the buckets of its lanes whose sizes are in (lo, SEG], 64 /
+// SEG at a time, one per segment of SEG lanes, one arrival per lane, and
+// writes their reservoirs.  `n`, `start`, `occ` are the candidates, their
+// position (as `fetch` takes it) and the old slots of each lane's own bucket
+// bk (any bucket per lane); fetch(bucket, start, occ, i) gives candidate i.
+template <uint32_t SEG, class Fetch>
+__device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, uint64_t bk, uint32_t n,
+                                                         uint32_t start, uint32_t occ, uint32_t lo,
+                                                         const Fetch& fetch) {
+  constexpr uint32_t G = 64 / SEG;
+  const uint32_t lane = threadIdx.x & 63, seg = lane / SEG, sl = lane % SEG;
+  const uint32_t R = (uint32_t)a.R;
+  uint64_t mm = __ballot(n > lo && n <= SEG);
+  while (mm) {
+    // pop up to G buckets; segment g takes the g-th (segments past the last get none)
+    uint32_t my_src = 64;
+#pragma unroll
+    for (uint32_t g = 0; g < G; ++g) {
+      const uint32_t src = mm ? (uint32_t)__ffsll((unsigned long long)mm) - 1 : 64u;
+      if (mm) mm &= mm - 1;
+      if (seg == g) my_src = src;
+    }
+    const bool has = my_src < 64;
+    const uint32_t bn = (uint32_t)__shfl((int)n, has ? (int)my_src : 0, 64);
+    const uint32_t bs = (uint32_t)__shfl((int)start, has ? (int)my_src : 0, 64);
+    const uint32_t bo = (uint32_t)__shfl((int)occ, has ? (int)my_src : 0, 64);
+    // (bucket indices are below 2^32)
+    const uint64_t bb = (uint32_t)__shfl((int)(uint32_t)bk, has ? (int)my_src : 0, 64);
+    const uint32_t t = (uint32_t)(bb / a.M);
+    const bool live = has && sl < bn;
+    const uint64_t v = live ? priority(a.s_p, t, fetch(bb, bs, bo, sl)) : ~0ull;
+    const uint64_t sorted = segment_bitonic_sort<SEG>(v);
+    if (live && sl < R) a.index[bb * a.S + kSlot0 + sl] = (int32_t)(uint32_t)sorted;
+  }
+}
+
+// Thread per bucket.  Buckets with at most kSmall arrivals: each thread ranks
+// its arrivals against each other in registers.  Buckets with kSmall < n <=
+// kMid: the wave sorts them in registers, one arrival per lane, four at a
+// time up to 16 arrivals and two at a time up to 32.  Larger buckets are listed (with
+// their start and size) for the LDS kernel; they are rare, so their appends
+// are few.
+// The select of one bucket per lane; every lane of the wave calls it (the
+// appends and the lane-segment sorts work across the wave).  fetch(bucket,
+// start, occ, i) gives candidate i of a bucket (start, occ: as the lane
+// passed them); the work items of mid-size and large buckets carry gstart,
+// the bucket's first slot in `staged`, where their kernels read them.
+template <class Fetch>
+__device__ __forceinline__ void select_lanes(const SelectArgs& a, uint64_t bk, bool in, uint32_t nn, uint32_t old,
+                                             uint32_t start, uint32_t gstart, const Fetch& fetch) {
+  const uint32_t R = (uint32_t)a.R;
+  const uint32_t occ = old < R ? old : R;   // reservoir slots that take part
+  const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
+  int32_t* res = a.index + bk * (uint64_t)a.S;
+  if (in) res[0] = (int32_t)(old + nn);
+  const bool mid = n > kMid && n <= kRegMax;
+  const bool big = n > kRegMax;
+  const uint32_t pm = wave_append(&a.wl_len[0], mid);
+  if (mid) a.work[pm] = make_uint4((uint32_t)bk, gstart, n, occ);
+  const uint32_t pb = wave_append(&a.wl_len[1], big);
+  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, gstart, n, occ);
+  if (n >= 1 && n <= (uint32_t)kSmall) {
+    const uint32_t t = (uint32_t)(bk / a.M);
+    // every candidate is fetched before any is used (past the last one the
+    // last is fetched again)
+    uint32_t idc[kSmall];
+#pragma unroll
+    for (int i = 0; i < kSmall; ++i) idc[i] = fetch(bk, start, occ, (uint32_t)i < n ? (uint32_t)i : n - 1);
+    uint64_t pk[kSmall];
+#pragma unroll
+    for (int i = 0; i < kSmall; ++i) pk[i] = (uint32_t)i < n ? priority(a.s_p, t, idc[i]) : ~0ull;
+#pragma unroll
+    for (int i = 0; i < kSmall; ++i) {
+      if ((uint32_t)i >= n) break;
+      int r = 0;
+#pragma unroll
+      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i] || (pk[j] == pk[i] && j < i);
+      if (r < a.R) res[kSlot0 + r] = (int32_t)(uint32_t)pk[i];
+    }
+  }
+  // every lane of the wave is still here: the mid-size buckets, several per
+  // wave when they are small enough
+  sort_buckets_by_segments<16>(a, bk, n, start, occ, (uint32_t)kSmall, fetch);
+  sort_buckets_by_segments<32>(a, bk, n, start, occ, 16u, fetch);
+  sort_buckets_by_segments<64>(a, bk, n, start, occ, 32u, fetch);
+}
+
+__global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
+  const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool in = bk < a.n_buckets;
+  const uint32_t nn = in ? a.newcnt[bk] : 0u;
+  const uint32_t old = (in && a.append) ? (uint32_t)a.index[bk * (uint64_t)a.S] : 0u;
+  const uint32_t start = in ? a.seg[bk] : 0u;
+  select_lanes(a, bk, in, nn, old, start, start,
+               [&](uint64_t b, uint32_t st, uint32_t oc, uint32_t i) { return candidate(a, b, st, oc, i); });
+}
+
 // ---- two-level partition (buckets that receive few arrivals each)
 //   tile    : block (t, tile of kTileE entries of keys_t[t]) counting-sorts
 //             its entries by chunk of CH buckets in LDS and writes them back
@@ -306,8 +461,10 @@ __global__ __launch_bounds__(kScanThreads) void scan_tiles_kernel(const uint32_t
 //   scan    : chunk_base = exclusive prefix of the chunk totals (table-major)
 //   chunk   : block (t, chunk) reads the chunk's run of every tile, histograms
 //             it by bucket in LDS, writes newcnt and seg of its CH buckets,
-//             then places each row id in the chunk's region of `staged`,
-//             which is small enough for its partial lines to merge in L2
+//             then places each row id in the chunk's region of `staged`
+//             (assembled in LDS when it fits); when the index is replaced
+//             (no append) the same block then selects its buckets, reading
+//             their candidates from that region, as bucket_select_small does
 // It produces the same newcnt, seg and (up to the order inside a bucket's
 // run) staged as the one-level partition.
 constexpr uint32_t kTileE = 8192;        // entries per tile (13 bits of row offset)
@@ -327,6 +484,8 @@ struct TwoArgs {
   uint32_t chb, n_chunks, n_tiles;
   uint32_t id_base, row_mod;
   uint32_t out_cap;         // ids a chunk may assemble in LDS
+  int fused;                // select the chunk's buckets here (no append)
+  SelectArgs sel;
 };
 
 __global__ __launch_bounds__(256) void tile_partition_kernel(TwoArgs a) {
@@ -442,14 +601,16 @@ __global__ __launch_bounds__(256) void chunk_scatter_kernel(TwoArgs a) {
   // 1. histogram of the chunk's buckets
   for_each_entry([&](uint32_t x, uint32_t) { atomicAdd(&hc[x & (ch - 1)], 1u); });
   __syncthreads();
-  // 2. counts and first slots of the chunk's buckets; the counts become cursors
+  // 2. counts and first slots of the chunk's buckets (thread i owns buckets
+  // i * q .. i * q + q - 1); the counts become cursors
   constexpr uint32_t kPer = kMaxCh2 / 256;
-  uint32_t v[kPer];
+  const uint32_t q = ch >= 256 ? ch / 256 : 1u;
+  uint32_t v[kPer], loff[kPer];
   uint32_t sum = 0;
 #pragma unroll
   for (uint32_t i = 0; i < kPer; ++i) {
-    const uint32_t j = threadIdx.x * kPer + i;
-    v[i] = j < cl ? hc[j] : 0u;
+    const uint32_t j = threadIdx.x * q + i;
+    v[i] = (i < q && j < cl) ? hc[j] : 0u;
     sum += v[i];
   }
   uint32_t total;
@@ -459,8 +620,9 @@ __global__ __launch_bounds__(256) void chunk_scatter_kernel(TwoArgs a) {
   __syncthreads();
 #pragma unroll
   for (uint32_t i = 0; i < kPer; ++i) {
-    const uint32_t j = threadIdx.x * kPer + i;
-    if (j < cl) {
+    const uint32_t j = threadIdx.x * q + i;
+    loff[i] = run_off;
+    if (i < q && j < cl) {
       a.newcnt[b0 + j] = v[i];
       a.seg[b0 + j] = base + run_off;
       hc[j] = run_off;
@@ -486,150 +648,23 @@ __global__ __launch_bounds__(256) void chunk_scatter_kernel(TwoArgs a) {
     __syncthreads();
     for (uint32_t i = threadIdx.x; i < total; i += 256) a.staged[base + i] = (int32_t)outb[i];
   }
-}
-
-struct SelectArgs {
-  int32_t* index;          // reservoir b: count at index[b * S] (in when appending, and out),
-                           // slot i at index[b * S + kSlot0 + i]
-  uint32_t S;
-  const uint32_t* newcnt;  // the batch's arrivals per bucket
-  const uint32_t* seg;     // their first staged slot
-  const int32_t* staged;
-  uint4* work;          // [nb] {bucket, first staged slot, candidates, old slots}
-                        // of the large buckets, from the back
-  uint32_t* wl_len;     // [2] buckets listed: [0] mid-size (from the front of
-                        // `work`), [1] large (from the back)
-  uint64_t n_buckets;
-  uint64_t s_p;
-  uint32_t M;
-  int R;
-  int append;           // 1: merge with the reservoirs already in the index
-};
-
-// Candidate i of bucket bk: its first `occ` are the ids already in the
-// reservoir (appending), the rest the batch's arrivals.
-__device__ __forceinline__ uint32_t candidate(const SelectArgs& a, uint64_t bk, uint32_t start, uint32_t occ,
-                                              uint32_t i) {
-  return i < occ ? (uint32_t)a.index[bk * (uint64_t)a.S + kSlot0 + i] : (uint32_t)a.staged[start + i - occ];
-}
-
-constexpr uint32_t kMid = 64;   // arrivals handled by one wave in registers, one per lane
-constexpr uint32_t kRegMax = 256;  // arrivals sorted in registers, up to four per lane
-
-// Appends for the lanes where pred holds, with one atomic per wave; returns
-// each such lane's slot.
-__device__ __forceinline__ uint32_t wave_append(uint32_t* counter, bool pred) {
-  const uint64_t m = __ballot(pred);
-  if (m == 0) return 0;
-  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)m) - 1;
-  uint32_t base = 0;
-  if ((threadIdx.x & 63) == leader) base = atomicAdd(counter, (uint32_t)__popcll(m));
-  base = (uint32_t)__builtin_amdgcn_readlane((int)base, (int)leader);
-  return base + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-}
-
-// Ascending sort of one 64-bit value per lane within each aligned segment of
-// SEG lanes (SEG a power of two <= 64), all segments at once.
-template <uint32_t SEG>
-__device__ __forceinline__ uint64_t segment_bitonic_sort(uint64_t v) {
-  const uint32_t lane = threadIdx.x & 63;
+  if (!a.fused) return;
+  // 4. the select of the chunk's buckets, candidates from the LDS region (or
+  // from `staged`, which the barrier makes visible to the workgroup); the
+  // mid-size and large buckets go on to their kernels through the work lists
+  __syncthreads();
 #pragma unroll
-  for (uint32_t k = 2; k <= SEG; k <<= 1) {
-#pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      const uint64_t o = xor_lane64(v, j);
-      const uint64_t mn = v < o ? v : o, mx = v < o ? o : v;
-      const bool up = k == SEG || (lane & k) == 0;
-      v = (((lane & j) == 0) == up) ? mn : mx;
-    }
+  for (uint32_t i = 0; i < kPer; ++i) {
+    if (i >= q) break;
+    const uint32_t j = threadIdx.x * q + i;
+    const bool in = j < cl;
+    if (in_lds)
+      select_lanes(a.sel, b0 + j, in, in ? v[i] : 0u, 0u, loff[i], base + loff[i],
+                   [&](uint64_t, uint32_t st, uint32_t, uint32_t k) { return outb[st + k]; });
+    else
+      select_lanes(a.sel, b0 + j, in, in ? v[i] : 0u, 0u, loff[i], base + loff[i],
+                   [&](uint64_t, uint32_t st, uint32_t, uint32_t k) { return (uint32_t)a.staged[base + st + k]; });
   }
-  return v;
-}
-
-// The wave sorts the buckets of its lanes whose sizes are in (lo, SEG], 64 /
-// SEG at a time, one per segment of SEG lanes, one arrival per lane, and
-// writes their reservoirs.  `n`, `start` are the bucket size and first staged
-// slot of each lane's own bucket bk.
-template <uint32_t SEG>
-__device__ __forceinline__ void sort_buckets_by_segments(const SelectArgs& a, uint64_t bk, uint32_t n,
-                                                         uint32_t start, uint32_t occ, uint32_t lo) {
-  constexpr uint32_t G = 64 / SEG;
-  const uint32_t lane = threadIdx.x & 63, seg = lane / SEG, sl = lane % SEG;
-  const uint32_t R = (uint32_t)a.R;
-  uint64_t mm = __ballot(n > lo && n <= SEG);
-  while (mm) {
-    // pop up to G buckets; segment g takes the g-th (segments past the last get none)
-    uint32_t my_src = 64;
-#pragma unroll
-    for (uint32_t g = 0; g < G; ++g) {
-      const uint32_t src = mm ? (uint32_t)__ffsll((unsigned long long)mm) - 1 : 64u;
-      if (mm) mm &= mm - 1;
-      if (seg == g) my_src = src;
-    }
-    const bool has = my_src < 64;
-    const uint32_t bn = (uint32_t)__shfl((int)n, has ? (int)my_src : 0, 64);
-    const uint32_t bs = (uint32_t)__shfl((int)start, has ? (int)my_src : 0, 64);
-    const uint32_t bo = (uint32_t)__shfl((int)occ, has ? (int)my_src : 0, 64);
-    const uint64_t bb = bk - lane + (has ? my_src : 0);
-    const uint32_t t = (uint32_t)(bb / a.M);
-    const bool live = has && sl < bn;
-    const uint64_t v = live ? priority(a.s_p, t, candidate(a, bb, bs, bo, sl)) : ~0ull;
-    const uint64_t sorted = segment_bitonic_sort<SEG>(v);
-    if (live && sl < R) a.index[bb * a.S + kSlot0 + sl] = (int32_t)(uint32_t)sorted;
-  }
-}
-
-// Thread per bucket.  Buckets with at most kSmall arrivals: each thread ranks
-// its arrivals against each other in registers.  Buckets with kSmall < n <=
-// kMid: the wave sorts them in registers, one arrival per lane, four at a
-// time up to 16 arrivals and two at a time up to 32.  Larger buckets are listed (with
-// their start and size) for the LDS kernel; they are rare, so their appends
-// are few.
-__global__ __launch_bounds__(256) void bucket_select_small_kernel(SelectArgs a) {
-  const uint64_t bk = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const bool in = bk < a.n_buckets;
-  const uint32_t R = (uint32_t)a.R;
-  const uint32_t nn = in ? a.newcnt[bk] : 0u;
-  const uint32_t old = (in && a.append) ? (uint32_t)a.index[bk * (uint64_t)a.S] : 0u;
-  const uint32_t occ = old < R ? old : R;   // reservoir slots that take part
-  const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
-  const uint32_t start = in ? a.seg[bk] : 0u;
-  if (in) a.index[bk * (uint64_t)a.S] = (int32_t)(old + nn);
-  const bool mid = n > kMid && n <= kRegMax;
-  const bool big = n > kRegMax;
-  const uint32_t pm = wave_append(&a.wl_len[0], mid);
-  if (mid) a.work[pm] = make_uint4((uint32_t)bk, start, n, occ);
-  const uint32_t pb = wave_append(&a.wl_len[1], big);
-  if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, start, n, occ);
-  if (n >= 1 && n <= (uint32_t)kSmall) {
-    const uint32_t t = (uint32_t)(bk / a.M);
-    uint32_t idc[kSmall];
-    if (!a.append) {
-      // the candidates are one run of `staged`: every load is issued before
-      // any is used (past the run's end the last one is read again)
-#pragma unroll
-      for (int i = 0; i < kSmall; ++i) idc[i] = (uint32_t)a.staged[start + ((uint32_t)i < n ? (uint32_t)i : n - 1)];
-    } else {
-#pragma unroll
-      for (int i = 0; i < kSmall; ++i) idc[i] = (uint32_t)i < n ? candidate(a, bk, start, occ, (uint32_t)i) : 0u;
-    }
-    uint64_t pk[kSmall];
-#pragma unroll
-    for (int i = 0; i < kSmall; ++i) pk[i] = (uint32_t)i < n ? priority(a.s_p, t, idc[i]) : ~0ull;
-#pragma unroll
-    for (int i = 0; i < kSmall; ++i) {
-      if ((uint32_t)i >= n) break;
-      int r = 0;
-#pragma unroll
-      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i] || (pk[j] == pk[i] && j < i);
-      if (r < a.R) a.index[bk * (uint64_t)a.S + kSlot0 + r] = (int32_t)(uint32_t)pk[i];
-    }
-  }
-  // every lane of the wave is still here: the mid-size buckets, several per
-  // wave when they are small enough
-  sort_buckets_by_segments<16>(a, bk, n, start, occ, (uint32_t)kSmall);
-  sort_buckets_by_segments<32>(a, bk, n, start, occ, 16u);
-  sort_buckets_by_segments<64>(a, bk, n, start, occ, 32u);
 }
 
 // Ascending bitonic sort of the wave's 64 * KPL values, element e = lane * KPL
@@ -928,6 +963,24 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   sm.P = c.P;
   hipLaunchKernelGGL(keys_transpose_kernel, dim3(g.np / 64, (c.L + 63) / 64), dim3(256), 0, s, keys,
                      (uint32_t)n_rows, (uint32_t)c.L, g.np, w.keys_t, sm);
+  SelectArgs a;
+  a.index = index;
+  a.S = c.S;
+  a.newcnt = w.newcnt;
+  a.seg = w.seg;
+  a.staged = w.staged;
+  a.work = w.work;
+  a.wl_len = w.wl_len;
+  a.n_buckets = g.nb;
+  a.s_p = c.seeds.s_p;
+  a.M = c.shared ? 1u : c.M;  // priority salt: the table, or the shared reservoir itself
+  a.R = c.R;
+  a.append = append ? 1 : 0;
+  // The chunk blocks select their own buckets when those receive many
+  // arrivals each (most go on to the wave-per-bucket kernels anyway); with
+  // few arrivals a thread per bucket across the whole index is faster than
+  // a chunk block's threads taking several buckets each.
+  const bool fused = g.two_level && !append && (double)g.np_part >= 16.0 * (double)g.Mp;
   if (g.two_level) {
     const uint64_t chunks = (uint64_t)g.Lp * g.n_chunks2;
     if ((e = launch_fill_u32(w.chunk_tot, chunks, 0u, s)) != hipSuccess) return e;
@@ -964,6 +1017,8 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
     while (cap <= 8192 && (double)cap < 1.25 * per_chunk) cap <<= 1;
     if (cap > 8192) cap = 0;
     ta.out_cap = cap;
+    ta.fused = fused ? 1 : 0;
+    ta.sel = a;
     const size_t lds_chunk = sizeof(uint32_t) * ((1u << g.chb) + 2 * kTB + cap);
     if ((e = allow_lds(reinterpret_cast<const void*>(&chunk_scatter_kernel), lds_chunk)) != hipSuccess) return e;
     hipLaunchKernelGGL(chunk_scatter_kernel, dim3(g.n_chunks2, g.Lp), dim3(256), lds_chunk, s, ta);
@@ -995,20 +1050,8 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
                      w.partoff, g.nb, g.n_slices, w.newcnt, w.seg);
   hipLaunchKernelGGL(part_scatter_kernel, dim3(blocks), dim3(kPartThreads), lds, s, pa);
   }
-  SelectArgs a;
-  a.index = index;
-  a.S = c.S;
-  a.newcnt = w.newcnt;
-  a.seg = w.seg;
-  a.staged = w.staged;
-  a.work = w.work;
-  a.wl_len = w.wl_len;
-  a.n_buckets = g.nb;
-  a.s_p = c.seeds.s_p;
-  a.M = c.shared ? 1u : c.M;  // priority salt: the table, or the shared reservoir itself
-  a.R = c.R;
-  a.append = append ? 1 : 0;
-  hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
+  if (!fused)
+    hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_select_mid_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   return hipGetLastError();
