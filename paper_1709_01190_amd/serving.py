@@ -7,7 +7,11 @@ with their own k.  Two servers share one interface:
   (one HIP stream) is free and its device memory fits the HBM budget; each
   admitted request runs flash_query_batch on its own stream, so requests that
   arrive while others are on the GPU start at once and overlap on the device.
-  Completion is polled with events; latency = completion seen - arrival.
+  Completion is polled with events; latency = completion seen - arrival.  A
+  completed request's lists are copied out of its slot's pinned buffers in
+  chunks, one per pass of the loop, so that a large result does not hold up
+  the admission of the requests behind it; the slot is free again once
+  drained.
 * BatchAllServer: the plain baseline.  While one batch runs, arrivals wait;
   when it ends, everything that has arrived (within the budget) is
   concatenated into one batch, queried with the largest k of the batch, and
@@ -168,6 +172,12 @@ class GpuExecutor:
         oi_h, oc_h = slot.pop("out")
         return (oi_h.numpy()[: n * k].reshape(n, k).copy(), oc_h.numpy()[: n * k].reshape(n, k).copy())
 
+    def result_views(self, slot, n: int, k: int):
+        """The completed request's lists (flat, n * k each) as views of the
+        slot's pinned buffers, valid until the slot is launched again."""
+        oi_h, oc_h = slot.pop("out")
+        return oi_h.numpy()[: n * k], oc_h.numpy()[: n * k]
+
 
 # ---------------------------------------------------------------- servers
 
@@ -178,6 +188,8 @@ def _reserve(executor, slot, n: int, nnz: int, k: int) -> None:
 
 class ContinuousServer:
     """Continuous batching: admit by arrival, a free slot and the HBM budget."""
+
+    drain_chunk = 1 << 16   # list entries copied out of a completed slot per loop pass
 
     def __init__(self, executor, budget_bytes: int = 4 << 30, slots: int = 8):
         self.ex = executor
@@ -200,20 +212,38 @@ class ContinuousServer:
         pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
         free = list(range(len(self.slots)))
         busy: Dict[int, tuple] = {}
+        draining: collections.deque = collections.deque()   # [slot, request, copied, views]
+        views = hasattr(self.ex, "result_views")
         in_use = 0
         t0 = clock()
-        while pending or busy:
+        while pending or busy or draining:
             now = clock() - t0
             progressed = False
             for si in list(busy):
                 if self.ex.done(self.slots[si]):
                     seen = clock() - t0
                     r, nbytes = busy.pop(si)
-                    r.out_ids, r.out_counts = self.ex.result(self.slots[si], r.n, r.k)
                     r.done = seen
-                    in_use -= nbytes
-                    free.append(si)
+                    in_use -= nbytes          # the device memory is free; the pinned lists are not yet
+                    if views:
+                        r.out_ids = np.empty((r.n, r.k), np.int32)
+                        r.out_counts = np.empty((r.n, r.k), np.int32)
+                        draining.append([si, r, 0, self.ex.result_views(self.slots[si], r.n, r.k)])
+                    else:
+                        r.out_ids, r.out_counts = self.ex.result(self.slots[si], r.n, r.k)
+                        free.append(si)
                     progressed = True
+            if draining:
+                d = draining[0]
+                si, r, pos, (vi, vc) = d
+                end = min(pos + self.drain_chunk, r.n * r.k)
+                r.out_ids.reshape(-1)[pos:end] = vi[pos:end]
+                r.out_counts.reshape(-1)[pos:end] = vc[pos:end]
+                d[2] = end
+                if end >= r.n * r.k:
+                    draining.popleft()
+                    free.append(si)
+                progressed = True
             now = clock() - t0
             # one admission per pass, so completions are seen between launches
             if pending and pending[0].arrival <= now and free:
@@ -231,7 +261,7 @@ class ContinuousServer:
                     self.ex.launch(self.slots[si], r.row_ptr, r.col_idx, r.k)
                     busy[si] = (r, need)
                     progressed = True
-            if not progressed and not busy and pending:
+            if not progressed and not busy and not draining and pending:
                 wait = pending[0].arrival - (clock() - t0)
                 if wait > 0:
                     time.sleep(min(wait, 1e-3))
