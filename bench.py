@@ -54,7 +54,7 @@ def main():
     ap.add_argument("--serving-repeats", type=int, default=3, help="serving: timed runs per rate")
     ap.add_argument("--serving-leg", default="1e6,2e6",
                     help="graph workloads: offered rates of the short serving leg on the URL-shaped "
-                         "index (2,000 requests each, after 300 untimed); empty skips it")
+                         "index (6,000 requests each, after 1,000 untimed); empty skips it")
     ap.add_argument("--slots", type=int, default=8, help="serving: requests in flight at once (streams)")
     ap.add_argument("--recall-queries", type=int, default=None,
                     help="sampled queries (graph workloads: rows) scored against brute-force "
@@ -218,10 +218,10 @@ def main():
     if args.serving_leg and args.workload == "webspam":
         env = _url_serving_setup()
         rates = [float(x) for x in args.serving_leg.split(",")]
-        table = _serving_rates(env, rates, 2000, 300, 1, args.slots, 4 << 30)
+        table = _serving_rates(env, rates, 6000, 1000, 1, args.slots, 4 << 30)
         serving_leg = {"workload": "url-shaped serving (2.4M-row index; batches of 1..4096 queries, "
                                    "k in {10, 50, 200}, Poisson arrivals)",
-                       "requests_per_rate": 2000, "warmup_requests": 300, "slots": args.slots,
+                       "requests_per_rate": 6000, "warmup_requests": 1000, "slots": args.slots,
                        "rates": [{"offered_qps": r["offered_qps"],
                                   "continuous": {x: r["continuous"][x] for x in ("p50_ms", "p99_ms", "qps")},
                                   "batch_all": {x: r["batch_all"][x] for x in ("p50_ms", "p99_ms", "qps")},
