@@ -410,14 +410,16 @@ __device__ __forceinline__ void select_lanes(const SelectArgs& a, uint64_t bk, b
   const uint32_t occ = old < R ? old : R;   // reservoir slots that take part
   const uint32_t n = nn ? occ + nn : 0u;    // candidates (none: the bucket is unchanged)
   int32_t* res = a.index + bk * (uint64_t)a.S;
-  if (in) res[0] = (int32_t)(old + nn);
+  const bool small = n >= 1 && n <= (uint32_t)kSmall;
+  // (a small bucket writes its header with its slots below)
+  if (in && !small) res[0] = (int32_t)(old + nn);
   const bool mid = n > kMid && n <= kRegMax;
   const bool big = n > kRegMax;
   const uint32_t pm = wave_append(&a.wl_len[0], mid);
   if (mid) a.work[pm] = make_uint4((uint32_t)bk, gstart, n, occ);
   const uint32_t pb = wave_append(&a.wl_len[1], big);
   if (big) a.work[a.n_buckets - 1 - pb] = make_uint4((uint32_t)bk, gstart, n, occ);
-  if (n >= 1 && n <= (uint32_t)kSmall) {
+  if (small) {
     const uint32_t t = (uint32_t)(bk / a.M);
     // every candidate is fetched before any is used (past the last one the
     // last is fetched again)
@@ -427,14 +429,24 @@ __device__ __forceinline__ void select_lanes(const SelectArgs& a, uint64_t bk, b
     uint64_t pk[kSmall];
 #pragma unroll
     for (int i = 0; i < kSmall; ++i) pk[i] = (uint32_t)i < n ? priority(a.s_p, t, idc[i]) : ~0ull;
+    // Batcher's odd-even merge network for 8 (19 compare-exchanges; the
+    // priorities are distinct, absent ones ~0 sort last)
+    constexpr int kNet[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2},
+                                 {5, 6}, {0, 4}, {1, 5}, {2, 6}, {3, 7}, {2, 4}, {3, 5}, {1, 2}, {3, 4},
+                                 {5, 6}};
 #pragma unroll
-    for (int i = 0; i < kSmall; ++i) {
-      if ((uint32_t)i >= n) break;
-      int r = 0;
-#pragma unroll
-      for (int j = 0; j < kSmall; ++j) r += pk[j] < pk[i] || (pk[j] == pk[i] && j < i);
-      if (r < a.R) res[kSlot0 + r] = (int32_t)(uint32_t)pk[i];
+    for (int c = 0; c < 19; ++c) {
+      const uint64_t x = pk[kNet[c][0]], y = pk[kNet[c][1]];
+      pk[kNet[c][0]] = x < y ? x : y;
+      pk[kNet[c][1]] = x < y ? y : x;
     }
+    // header, then slots 0..7 (words past min(n, R) are not part of the
+    // index; S >= 32 words, so all twelve lie inside the reservoir): three
+    // 16-byte stores into one line
+    uint4* r4 = reinterpret_cast<uint4*>(res);
+    r4[0] = make_uint4(old + nn, 0u, 0u, 0u);
+    r4[1] = make_uint4((uint32_t)pk[0], (uint32_t)pk[1], (uint32_t)pk[2], (uint32_t)pk[3]);
+    if (n > 4 && R > 4) r4[2] = make_uint4((uint32_t)pk[4], (uint32_t)pk[5], (uint32_t)pk[6], (uint32_t)pk[7]);
   }
   // every lane of the wave is still here: the mid-size buckets, several per
   // wave when they are small enough
