@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -61,6 +62,8 @@ def main():
                          "exact Jaccard; 0 skips it")
     ap.add_argument("--rows", type=int, default=0, help="override the row count (parity/debug only)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="uneven: keep the default tuning")
+    ap.add_argument("--no-per-bucket", action="store_true", help="uneven: leave out the per-bucket baseline")
     ap.add_argument("--traffic-table", default=os.path.join(ROOT, "profiles", "hbm_traffic.txt"),
                     help="calibrated per-launch HBM bytes from rocprofv3 FETCH_SIZE/WRITE_SIZE runs")
     ap.add_argument("--copy-reps", type=int, default=1,
@@ -477,25 +480,49 @@ def uneven_bench(args):
     flash.flash_set_tuning(None)
     timed(persistent, args.warmup)
     default_ms = timed(persistent, args.steps)
-    # autotune on the first 128K queries
-    ns = min(nq, 131072)
-    srp, sci = qrp[:ns + 1], qci[: int(qrp[ns])]
-    soi = torch.empty(ns * kmax, dtype=torch.int32, device="cuda")
-    soc = torch.empty_like(soi)
-    sws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=ns, k=kmax)
-    best, best_ms = flash.flash_autotune_query_batch(p, index, spec.n_rows, srp, sci, kq[:ns].contiguous(),
-                                                     kmax, soi, soc, sws, reps=2, stream=stream)
-    log(f"autotuned on {ns} queries: {best.as_dict()} ({best_ms:.3f} ms)")
+    if args.no_autotune:
+        best = flash.flash_get_tuning()
+    else:
+        # autotune on the first 128K queries
+        ns = min(nq, 131072)
+        srp, sci = qrp[:ns + 1], qci[: int(qrp[ns])]
+        soi = torch.empty(ns * kmax, dtype=torch.int32, device="cuda")
+        soc = torch.empty_like(soi)
+        sws = flash.alloc_workspace(flash.OP_QUERY, p, n_queries=ns, k=kmax)
+        best, best_ms = flash.flash_autotune_query_batch(p, index, spec.n_rows, srp, sci, kq[:ns].contiguous(),
+                                                         kmax, soi, soc, sws, reps=2, stream=stream)
+        log(f"autotuned on {ns} queries: {best.as_dict()} ({best_ms:.3f} ms)")
     timed(persistent, args.warmup)
     tuned_ms = timed(persistent, args.steps)
     torch.cuda.synchronize()
+
+    # the query kernels alone, on the batch's precomputed keys (the same
+    # tuning): their time, and their algorithmic bytes per query = 4L (keys)
+    # + 4L (reservoir headers) + 4 per occupied slot + 8k (outputs)
+    qkeys = torch.empty(nq * L, dtype=torch.int32, device="cuda")
+    flash.flash_hash(p, qrp, qci, qkeys, stream=stream)
+    qoi, qoc = torch.empty_like(oi), torch.empty_like(oc)
+    kws = flash.alloc_workspace(flash.OP_QUERY_KEYS, p, n_queries=nq, k=kmax)
+
+    def query_only():
+        flash.flash_query_keys_mixed(p, index, spec.n_rows, qkeys, kq, kmax, qoi, qoc, kws, stream=stream)
+
+    timed(query_only, args.warmup)
+    query_ms = timed(query_only, args.steps)
+    M = p.M
+    counts = flash.index_parts(p, index)[0].reshape(L, M).long()
+    kk = qkeys.view(nq, L).long() & 0xFFFFFFFF
+    occ = torch.clamp(counts[torch.arange(L, device="cuda")[None, :], kk.clamp(0, M - 1)], max=R)
+    occ_sum = int(torch.where(kk < M, occ, torch.zeros_like(occ)).sum().item())
+    q_alg = nq * 8 * L + 4 * occ_sum + 8 * int(kq.long().sum().item())
+    same_query_only = bool(torch.equal(qoi, oi) and torch.equal(qoc, oc))
 
     # baseline: one launch per (size class, k) bucket, default tuning
     flash.flash_set_tuning(None)
     cls = torch.ceil(torch.log2(lens.double())).to(torch.int64)
     bucket_key = (cls * 1000 + kq.to(torch.int64)).cpu().numpy()
     buckets = []
-    for key in np.unique(bucket_key):
+    for key in (np.unique(bucket_key) if not args.no_per_bucket else []):
         sel = torch.from_numpy(np.nonzero(bucket_key == key)[0]).cuda()
         blen = lens[sel]
         brp = torch.zeros(sel.numel() + 1, dtype=torch.int64, device="cuda")
@@ -513,17 +540,22 @@ def uneven_bench(args):
         for sel, brp, bci, bk, boi, boc, bws in buckets:
             flash.flash_query_batch(p, index, spec.n_rows, brp, bci, bk, boi, boc, bws, stream=stream)
 
-    timed(per_bucket, args.warmup)
-    bucket_ms = timed(per_bucket, args.steps)
-    # identical lists: scatter the buckets back into query order
-    got_i = torch.full((nq, kmax), -1, dtype=torch.int32, device="cuda")
-    got_c = torch.zeros((nq, kmax), dtype=torch.int32, device="cuda")
-    for sel, brp, bci, bk, boi, boc, bws in buckets:
-        got_i[sel, :bk] = boi.view(-1, bk)
-        got_c[sel, :bk] = boc.view(-1, bk)
-    same = bool(torch.equal(got_i.view(-1), oi) and torch.equal(got_c.view(-1), oc))
+    same = same_query_only
+    bucket_ms = [math.nan]
+    if not args.no_per_bucket:
+        timed(per_bucket, args.warmup)
+        bucket_ms = timed(per_bucket, args.steps)
+        # identical lists: scatter the buckets back into query order
+        got_i = torch.full((nq, kmax), -1, dtype=torch.int32, device="cuda")
+        got_c = torch.zeros((nq, kmax), dtype=torch.int32, device="cuda")
+        for sel, brp, bci, bk, boi, boc, bws in buckets:
+            got_i[sel, :bk] = boi.view(-1, bk)
+            got_c[sel, :bk] = boc.view(-1, bk)
+        same = same and bool(torch.equal(got_i.view(-1), oi) and torch.equal(got_c.view(-1), oc))
     med = lambda v: float(np.median(v))
     t_p, t_b = med(tuned_ms), med(bucket_ms)
+    t_q = med(query_ms)
+    achieved = q_alg / (t_q * 1e6)
     out = {
         "metric": "uneven batch queries per second (40M-row click-log-shape index)",
         "value": round(nq / (t_p / 1e3), 1),
@@ -542,9 +574,16 @@ def uneven_bench(args):
                    "K": K, "L": L, "bits_per_hash": b, "R": R, "k": [10, 100]},
         "persistent_autotuned_ms": round(t_p, 3),
         "persistent_default_ms": round(med(default_ms), 3),
-        "per_bucket_ms": round(t_b, 3),
+        "per_bucket_ms": round(t_b, 3) if not args.no_per_bucket else None,
         "per_bucket_launches": len(buckets),
-        "speedup_vs_per_bucket": round(t_b / t_p, 3),
+        "speedup_vs_per_bucket": round(t_b / t_p, 3) if not args.no_per_bucket else None,
+        "roofline": {"bound": "hbm", "kernel": "count_topk kernels (the query on precomputed keys)",
+                     "achieved": round(achieved, 1), "peak": 8000.0, "unit": "GB/s",
+                     "frac": round(achieved / 8000.0, 4),
+                     "traffic": _traffic(args.traffic_table, "uneven", "count_topk")},
+        "query_only_ms": round(t_q, 3),
+        "query_alg_bytes": q_alg,
+        "occupied_ids_per_query": round(occ_sum / nq, 1),
         "tuning": best.as_dict(),
         "index_build_ms": round(med(build_ms), 3),
         "identical_lists": same,
