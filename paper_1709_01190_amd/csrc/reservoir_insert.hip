@@ -885,12 +885,13 @@ Geo geometry(const Cfg& c, int64_t n_rows) {
   g.nparts = g.nb * s;
   g.tiles = (g.nparts + kTile - 1) / kTile;
   // Two-level partition when the buckets receive few arrivals: chunks of
-  // at least Mp / 64 buckets (runs of ~128 entries per tile), halved down
-  // to Mp / 256 while a chunk's region of `staged` exceeds 64 KiB; taken
-  // if that region is at most 128 KiB and the histogram fits LDS.
+  // at least Mp / 128 buckets (runs of ~64 entries per tile; twice that
+  // measured slower, the chunk workgroups then hold twice the LDS), halved
+  // down to Mp / 256 while a chunk's region of `staged` exceeds 64 KiB;
+  // taken if that region is at most 128 KiB and the histogram fits LDS.
   const double per_bucket = (double)g.np_part / (double)g.Mp;
   uint32_t chb = 6;
-  while ((1ull << chb) * 64 < g.Mp) ++chb;
+  while ((1ull << chb) * 128 < g.Mp) ++chb;
   while (chb > 6 && (double)(1ull << chb) * per_bucket * 4.0 > 65536.0 && (1ull << (chb - 1)) * kMaxChunks2 >= g.Mp)
     --chb;
   g.chb = chb;
