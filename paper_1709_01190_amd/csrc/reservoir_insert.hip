@@ -765,8 +765,12 @@ __global__ __launch_bounds__(64) void bucket_select_mid_kernel(SelectArgs a) {
   }
 }
 
-// One wave per large bucket (n > kRegMax).
+// One wave per large bucket (n > kRegMax).  CAP priorities fit in LDS: 1024
+// when R <= 256 (the threshold keeps about 2R <= 512, between R and CAP), so
+// that twice as many waves fit a CU; 2048 above.
+template <uint32_t CAP>
 __global__ __launch_bounds__(64) void bucket_select_big_kernel(SelectArgs a) {
+  constexpr uint32_t kWaveCap = CAP;
   __shared__ uint64_t buf[kWaveCap];
   __shared__ uint32_t cnt_sh;
   const uint32_t lane = threadIdx.x;
@@ -1066,7 +1070,10 @@ hipError_t launch_insert(const Cfg& c, int64_t n_rows, const uint32_t* keys, uin
   if (!fused)
     hipLaunchKernelGGL(bucket_select_small_kernel, dim3((uint32_t)((g.nb + 255) / 256)), dim3(256), 0, s, a);
   hipLaunchKernelGGL(bucket_select_mid_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
-  hipLaunchKernelGGL(bucket_select_big_kernel, dim3(device_info().cus * 32), dim3(64), 0, s, a);
+  if (c.R <= 256)
+    hipLaunchKernelGGL(bucket_select_big_kernel<1024>, dim3(device_info().cus * 32), dim3(64), 0, s, a);
+  else
+    hipLaunchKernelGGL(bucket_select_big_kernel<kWaveCap>, dim3(device_info().cus * 32), dim3(64), 0, s, a);
   return hipGetLastError();
 }
 

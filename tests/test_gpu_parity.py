@@ -219,6 +219,34 @@ def test_insert_heavy_buckets(fl, orc, R):
     occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
 
 
+@pytest.mark.parametrize("R", [8, 128])
+def test_insert_sparse_buckets_with_a_hot_chunk(fl, orc, R):
+    # The two-level partition (few arrivals per bucket on average: 65,536
+    # buckets, ~2 arrivals each) with one chunk of buckets far above its
+    # LDS copy (the chunk's ids stored straight to the staged array), buckets
+    # of every select size (1..8, 9..64, 65..256, above) and appends on top.
+    import torch
+    say("insert sparse buckets with a hot chunk R", R)
+    rng = np.random.default_rng(40 + R)
+    K, L, b = 4, 2, 4
+    M = 1 << (K * b)
+    n = 150_000
+    keys = rng.integers(0, M, size=(n, L), dtype=np.int64).astype(np.uint32)
+    # rows 0..29,999 of table 0 land in buckets 0..99 (one chunk, ~300 each);
+    # a few single buckets get 20, 90, 300 and 3,000 arrivals
+    keys[:30_000, 0] = rng.integers(0, 100, size=30_000).astype(np.uint32)
+    for bkt, cnt, lo in ((40_000, 20, 40_000), (41_000, 90, 41_000), (42_000, 300, 42_000), (43_000, 3000, 43_000)):
+        keys[lo:lo + cnt, 1] = bkt
+    keys[rng.random((n, L)) < 0.01] = EMPTY
+    op = orc.params(K, L, b, R, seed=3)
+    ocounts, oids = orc.build_tables(op, keys)
+    p = fl.flash_params.make(K, L, b, R, seed=3)
+    index = gpu_insert(fl, p, keys)
+    occupied_equal(*host_index(fl, p, index), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+    index2 = _append_batches(fl, p, keys, [0, 20_000, 70_000, n], [1, 0, 2])
+    occupied_equal(*host_index(fl, p, index2), ocounts.reshape(-1), oids.reshape(-1), L, M, R)
+
+
 def test_insert_is_deterministic(fl):
     import torch
     say("insert determinism")
