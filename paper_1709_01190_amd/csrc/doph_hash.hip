@@ -52,32 +52,102 @@ __device__ __forceinline__ bool occupied(const uint32_t* occw, uint32_t j) {
   return (occw[j >> 5] >> (j & 31)) & 1u;
 }
 
-// Hashes one row with the whole wave; mins/occw/top_bin are the wave's LDS.
-template <bool POW2>
+// Densification probe t (1-based) of bin j: a bin given by fmix32 of (j, t).
+__device__ __forceinline__ uint32_t probe_bin(const HashArgs& a, uint32_t j, uint32_t t) {
+  return __umulhi(fmix32(((j << 16) | t) ^ a.s_d), (uint32_t)a.B);
+}
+
+// Source bin of empty bin j from probe t_first on: probes t_first..A, then
+// the nearest occupied bin to the right (cyclically).  The row has at least
+// one occupied bin.
+__device__ __forceinline__ uint32_t probe_from(const HashArgs& a, const uint32_t* occw, uint32_t j,
+                                               int t_first) {
+  for (int t = t_first; t <= a.A; ++t) {
+    const uint32_t p = probe_bin(a, j, (uint32_t)t);
+    if (occupied(occw, p)) return p;
+  }
+  const uint32_t nwords = ((uint32_t)a.B + 31) >> 5;
+  const uint32_t s0 = j + 1 == (uint32_t)a.B ? 0u : j + 1;
+  uint32_t w = s0 >> 5;
+  uint32_t bits = occw[w] & (0xFFFFFFFFu << (s0 & 31));
+  while (bits == 0) {
+    w = w + 1 == nwords ? 0 : w + 1;
+    bits = occw[w];
+  }
+  return w * 32 + (uint32_t)(__ffs(bits) - 1);
+}
+
+// Bins of at most kPreBins (PRE): each lane owns bins lane + 64 r, r < 4,
+// and holds their first kPreProbes probe bins as bytes in registers, worked
+// out once per wave; they depend on the bin and the seed only.
+constexpr int kPreRounds = 4;
+constexpr int kPreProbes = 8;
+constexpr int kPreBins = kPreRounds * kWave;  // 256: a bin fits a byte
+struct ProbeTable {
+  uint32_t w[kPreRounds][kPreProbes / 4];
+};
+
+__device__ __forceinline__ ProbeTable make_probe_table(const HashArgs& a) {
+  ProbeTable pt;
+  const uint32_t lane = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < kPreRounds; ++r) {
+    const uint32_t j = (uint32_t)r * kWave + lane;
+#pragma unroll
+    for (int q = 0; q < kPreProbes / 4; ++q) {
+      uint32_t w = 0;
+      if (j < (uint32_t)a.B)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int t = q * 4 + i + 1;
+          if (t <= a.A) w |= probe_bin(a, j, (uint32_t)t) << (8 * i);
+        }
+      pt.w[r][q] = w;
+    }
+  }
+  return pt;
+}
+
+// Hashes one row with the whole wave.  LDS: mins[B] bin minima, occw[B/32]
+// occupancy bits; with PRE also occ8[256], one occupancy byte per bin.
+template <bool POW2, bool PRE>
 __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_t* mins, uint32_t* occw,
-                                         uint32_t& top_bin) {
-  const int lane = threadIdx.x;
+                                         uint8_t* occ8, const ProbeTable& pt, uint32_t& top_bin) {
+  const uint32_t lane = threadIdx.x;
   const int B = a.B;
   const int nwords = (B + 31) >> 5;
-  const uintptr_t mis = ((uintptr_t)a.col_idx >> 2) & 3;  // element misalignment vs 16 B
-  {
-    int64_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
-    beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
-    end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
+  int64_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
+  beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
+  end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
 
-    for (int j = lane; j < B; j += kWave) mins[j] = kEmpty;
-    if (lane == 0) top_bin = kEmpty;
+  for (int j = lane; j < B; j += kWave) mins[j] = kEmpty;
+  if (lane == 0) top_bin = kEmpty;
+  __syncthreads();
+
+  if (beg == end) {  // empty row: all keys and codes are the empty marker
+    for (int t = lane; t < a.L; t += kWave) a.keys[row * a.L + t] = kEmpty;
+    if (a.codes)
+      for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = kEmpty;
     __syncthreads();
+    return;
+  }
 
-    if (beg == end) {  // empty row: all keys and codes are the empty marker
-      for (int t = lane; t < a.L; t += kWave) a.keys[row * a.L + t] = kEmpty;
-      if (a.codes)
-        for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = kEmpty;
-      __syncthreads();
-      return;
-    }
-
-    // 1. bin minima.  a0/a1: first/last 16-byte aligned element positions.
+  // 1. bin minima
+  if (end - beg <= 4 * kWave) {
+    // short row: one column id per lane and round, up to four rounds in flight
+    const int32_t* rp = a.col_idx + beg;
+    const uint32_t nn = (uint32_t)(end - beg);
+    uint32_t x[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + kWave * u < nn) x[u] = (uint32_t)__builtin_nontemporal_load(rp + lane + kWave * u);
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (lane + kWave * u < nn) add_column<POW2>(a, x[u], mins, &top_bin);
+  } else {
+    // long row: 16-byte loads between the first and last aligned element
+    // positions a0, a1; the unaligned ends one element per lane
+    const uintptr_t mis = ((uintptr_t)a.col_idx >> 2) & 3;  // element misalignment vs 16 B
     int64_t a0 = beg + (int64_t)((4 - ((uint64_t)(beg + mis) & 3)) & 3);
     int64_t a1 = end - (int64_t)((uint64_t)(end + mis) & 3);
     if (a0 >= a1) {
@@ -111,68 +181,87 @@ __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_
         }
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
 
-    // 2. occupancy bitmask
-    const uint32_t tb = top_bin;
-    for (int j0 = 0; j0 < B; j0 += kWave) {
-      const int j = j0 + lane;
-      const bool o = j < B && (mins[j] != kEmpty || (uint32_t)j == tb);
-      const uint64_t m = __ballot(o);
-      if (lane == 0) {
-        occw[j0 >> 5] = (uint32_t)m;
-        if ((j0 >> 5) + 1 < nwords) occw[(j0 >> 5) + 1] = (uint32_t)(m >> 32);
+  // 2. occupancy: bits (ballots) and, with PRE, bytes; own bins' in `own`
+  const uint32_t tb = top_bin;
+  uint32_t own = 0;
+  for (int j0 = 0; j0 < B; j0 += kWave) {
+    const uint32_t j = (uint32_t)j0 + lane;
+    const bool o = j < (uint32_t)B && (mins[j] != kEmpty || j == tb);
+    const uint64_t m = __ballot(o);
+    if (PRE) {
+      if (j < (uint32_t)B) occ8[j] = (uint8_t)o;
+      own |= (uint32_t)o << (j0 / kWave);
+    }
+    if (lane == 0) {
+      occw[j0 >> 5] = (uint32_t)m;
+      if ((j0 >> 5) + 1 < nwords) occw[(j0 >> 5) + 1] = (uint32_t)(m >> 32);
+    }
+  }
+  __syncthreads();
+
+  // 3. densification: only empty bins are written and only occupied bins
+  // are read, so bins can be filled in place.
+  if (PRE) {
+    // the first kPreProbes probes of a bin are read all at once; the first
+    // occupied one is the source, else the probes go on from kPreProbes + 1
+    const uint32_t tmask = a.A >= kPreProbes ? (1u << kPreProbes) - 1u : (1u << a.A) - 1u;
+    const int rounds = (B + kWave - 1) / kWave;
+#pragma unroll 1
+    for (int r = 0; r < rounds; ++r) {
+      const uint32_t j = (uint32_t)r * kWave + lane;
+      // this round's two table words (r is the same in every lane)
+      const uint32_t w0 = r == 0 ? pt.w[0][0] : r == 1 ? pt.w[1][0] : r == 2 ? pt.w[2][0] : pt.w[3][0];
+      const uint32_t w1 = r == 0 ? pt.w[0][1] : r == 1 ? pt.w[1][1] : r == 2 ? pt.w[2][1] : pt.w[3][1];
+      if (j < (uint32_t)B && !((own >> r) & 1u)) {
+        uint32_t hits = 0;
+#pragma unroll
+        for (int t = 0; t < kPreProbes; ++t)
+          hits |= (uint32_t)occ8[__builtin_amdgcn_ubfe(t < 4 ? w0 : w1, (t & 3) * 8, 8)] << t;
+        hits &= tmask;
+        uint32_t src;
+        if (hits) {
+          const uint32_t t = (uint32_t)(__ffs(hits) - 1);
+          src = __builtin_amdgcn_ubfe(t < 4 ? w0 : w1, (t & 3) * 8, 8);
+        } else {
+          src = probe_from(a, occw, j, kPreProbes + 1);
+        }
+        mins[j] = mins[src];
       }
     }
-    __syncthreads();
-
-    // 3. densification: only empty bins are written and only occupied bins
-    // are read, so bins can be filled in place.
+  } else {
     for (int j = lane; j < B; j += kWave) {
       if (occupied(occw, (uint32_t)j)) continue;
-      int src = -1;
-      for (int t = 1; t <= a.A; ++t) {
-        const uint32_t p = __umulhi(fmix32((((uint32_t)j << 16) | (uint32_t)t) ^ a.s_d), (uint32_t)B);
-        if (occupied(occw, p)) {
-          src = (int)p;
-          break;
-        }
-      }
-      if (src < 0) {  // nearest occupied bin to the right, cyclically
-        const uint32_t s0 = (uint32_t)(j + 1 == B ? 0 : j + 1);
-        uint32_t w = s0 >> 5;
-        uint32_t bits = occw[w] & (0xFFFFFFFFu << (s0 & 31));
-        while (bits == 0) {
-          w = (w + 1 == (uint32_t)nwords) ? 0 : w + 1;
-          bits = occw[w];
-        }
-        src = (int)(w * 32 + (uint32_t)(__ffs(bits) - 1));
-      }
-      mins[j] = mins[src];
+      mins[j] = mins[probe_from(a, occw, (uint32_t)j, 1)];
     }
-    __syncthreads();
-
-    // 4. keys (and codes)
-    for (int t = lane; t < a.L; t += kWave) {
-      uint32_t key = 0;
-      for (int j = 0; j < a.K; ++j) key |= (mins[t * a.K + j] & a.mask) << (a.b * j);
-      a.keys[row * a.L + t] = key;
-    }
-    if (a.codes)
-      for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = mins[j];
-    __syncthreads();
   }
+  __syncthreads();
+
+  // 4. keys (and codes)
+  for (int t = lane; t < a.L; t += kWave) {
+    uint32_t key = 0;
+    for (int j = 0; j < a.K; ++j) key |= (mins[t * a.K + j] & a.mask) << (a.b * j);
+    a.keys[row * a.L + t] = key;
+  }
+  if (a.codes)
+    for (int j = lane; j < B; j += kWave) a.codes[row * B + j] = mins[j];
+  __syncthreads();
 }
 
 // Static schedule: wave w hashes rows w, w + grid, ...  Dynamic schedule
 // (for batches of very uneven rows): each wave takes tiles of tile_rows
 // consecutive rows from a work counter until the tiles run out.
-template <bool POW2>
+template <bool POW2, bool PRE>
 __global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
   extern __shared__ uint32_t lds[];
-  uint32_t* mins = lds;              // [B]
-  uint32_t* occw = lds + a.B;        // [ceil(B / 32)]
+  uint8_t* occ8 = reinterpret_cast<uint8_t*>(lds);  // [256] (PRE)
+  uint32_t* mins = lds + (PRE ? kPreBins / 4 : 0);  // [B]
+  uint32_t* occw = mins + a.B;                       // [ceil(B / 32)]
   __shared__ uint32_t top_bin;
+  ProbeTable pt = {};
+  if (PRE) pt = make_probe_table(a);
   if (a.tile_ctr) {
     for (;;) {
       uint32_t t = 0;
@@ -181,10 +270,11 @@ __global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
       const int64_t r0 = (int64_t)t * a.tile_rows;
       if (r0 >= a.n_rows) break;
       const int64_t r1 = r0 + a.tile_rows < a.n_rows ? r0 + a.tile_rows : a.n_rows;
-      for (int64_t row = r0; row < r1; ++row) hash_row<POW2>(a, row, mins, occw, top_bin);
+      for (int64_t row = r0; row < r1; ++row) hash_row<POW2, PRE>(a, row, mins, occw, occ8, pt, top_bin);
     }
   } else {
-    for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) hash_row<POW2>(a, row, mins, occw, top_bin);
+    for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x)
+      hash_row<POW2, PRE>(a, row, mins, occw, occ8, pt, top_bin);
   }
 }
 
@@ -211,8 +301,13 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
   a.mask = c.mask;
   const bool pow2 = (c.B & (c.B - 1)) == 0;
   a.shift = pow2 ? 32 - (31 - __builtin_clz((unsigned)c.B)) : 0;
-  const size_t lds = sizeof(uint32_t) * ((size_t)c.B + (size_t)((c.B + 31) / 32));
-  const int64_t want = (int64_t)device_info().cus * 32;
+  const bool pre = c.B <= kPreBins;
+  const size_t lds = sizeof(uint32_t) * ((size_t)c.B + (size_t)((c.B + 31) / 32)) + (pre ? kPreBins : 0);
+  const void* kern = pow2 ? (pre ? (const void*)doph_hash_kernel<true, true> : (const void*)doph_hash_kernel<true, false>)
+                          : (pre ? (const void*)doph_hash_kernel<false, true> : (const void*)doph_hash_kernel<false, false>);
+  // as many one-wave blocks as fit the chip at once: with the static stride
+  // every block then starts at launch and no block runs behind the rest
+  const int64_t want = (int64_t)device_info().cus * resident_blocks(kern, lds);
   const int grid = (int)(n_rows < want ? n_rows : want);
   const int tile = tuning().hash_tile_rows;
   a.tile_ctr = tile > 0 ? tile_ctr : nullptr;
@@ -221,10 +316,9 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
     const hipError_t e = launch_fill_u32(a.tile_ctr, 1, 0u, s);
     if (e != hipSuccess) return e;
   }
-  if (pow2)
-    hipLaunchKernelGGL(doph_hash_kernel<true>, dim3(grid), dim3(64), lds, s, a);
-  else
-    hipLaunchKernelGGL(doph_hash_kernel<false>, dim3(grid), dim3(64), lds, s, a);
+  void* args[] = {&a};
+  const hipError_t e = hipLaunchKernel(kern, dim3(grid), dim3(64), args, lds, s);
+  if (e != hipSuccess) return e;
   return hipGetLastError();
 }
 

@@ -115,6 +115,34 @@ const Device& device_info() {
   return infos[dev];
 }
 
+int resident_blocks(const void* kernel, size_t lds_bytes) {
+  // cached per (kernel, LDS bytes, device); past 64 triples it is asked again
+  static std::mutex mu;
+  static const void* kern[64];
+  static size_t size[64];
+  static int devs[64], val[64];
+  static int n = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  {
+    std::lock_guard<std::mutex> lock(mu);
+    for (int i = 0; i < n; ++i)
+      if (kern[i] == kernel && size[i] == lds_bytes && devs[i] == dev) return val[i];
+  }
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, kernel, 64, lds_bytes) != hipSuccess || blocks < 1)
+    blocks = 8;
+  std::lock_guard<std::mutex> lock(mu);
+  if (n < 64) {
+    kern[n] = kernel;
+    size[n] = lds_bytes;
+    devs[n] = dev;
+    val[n] = blocks;
+    ++n;
+  }
+  return blocks;
+}
+
 hipError_t allow_lds(const void* kernel, size_t bytes) {
   if (bytes <= 64 * 1024) return hipSuccess;
   // the attribute is per (kernel, device); past 64 pairs it is simply set again

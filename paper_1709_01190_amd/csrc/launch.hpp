@@ -108,6 +108,10 @@ hipError_t launch_fill_strided_u32(uint32_t* p, uint64_t n, uint32_t stride, uin
 // first eager one.
 hipError_t allow_lds(const void* kernel, size_t bytes);
 
+// One-wave (64-thread) blocks of `kernel` with `lds_bytes` of dynamic LDS
+// that one CU holds at once.
+int resident_blocks(const void* kernel, size_t lds_bytes);
+
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace flashk

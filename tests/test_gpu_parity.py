@@ -139,7 +139,8 @@ def test_hash_tiny_workload(fl, orc):
 
 
 @pytest.mark.parametrize("K,L,b,A", [(4, 16, 4, 64), (5, 32, 3, 64), (1, 1, 16, 64), (16, 256, 1, 64),
-                                     (3, 3, 5, 0), (4, 64, 4, 2), (2, 70, 7, 64)])
+                                     (3, 3, 5, 0), (4, 64, 4, 2), (2, 70, 7, 64), (5, 32, 3, 12),
+                                     (3, 40, 4, 8)])
 def test_hash_edge_rows(fl, orc, K, L, b, A):
     say("hash edge rows", K, L, b, A)
     rng = np.random.default_rng(K * 1000 + L)
@@ -150,7 +151,10 @@ def test_hash_edge_rows(fl, orc, K, L, b, A):
     rows = [[], [5], [1, 2], list(range(63)), list(range(64)), list(range(65)),
             rng.integers(-(1 << 31), (1 << 31) - 1, size=1000).tolist(),
             [7, 7, 7, 3, 3, 9], rng.permutation(300).tolist(), [top_col], [top_col, 11, 12],
-            rng.integers(0, 1 << 20, size=5000).tolist(), [], [0]]
+            rng.integers(0, 1 << 20, size=5000).tolist(), [], [0],
+            # either side of the one-id-per-lane path for short rows
+            rng.integers(0, 1 << 20, size=256).tolist(), rng.integers(0, 1 << 20, size=257).tolist(),
+            rng.integers(0, 1 << 20, size=129).tolist()]
     rp, ci = csr_from_rows(rows)
     p = fl.flash_params.make(K, L, b, 8, seed=seed, densify_attempts=A)
     okeys, ocodes = orc.doph(orc.params(K, L, b, 8, seed=seed, densify_attempts=A), rp, ci,
