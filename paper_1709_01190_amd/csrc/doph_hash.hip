@@ -162,7 +162,7 @@ __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_
     }
     const int64_t nvec = (a1 - a0) >> 2;
     const u32x4* vp = reinterpret_cast<const u32x4*>(a.col_idx + a0);
-    constexpr int U = 12;
+    constexpr int U = 8;
     for (int64_t v = lane; v < nvec; v += (int64_t)kWave * U) {
       u32x4 x[U];
 #pragma unroll
