@@ -829,10 +829,11 @@ __global__ __launch_bounds__(64 * NW) void count_topk_block_kernel(QueryArgs a) 
 // distinct (the usual case: a query meets a few ids in several tables and
 // many once).  One wave per query keeps all its candidates in registers (up
 // to 32 per lane) and needs no full counting table:
-//   a. every candidate sets its two bits (in one word) of a 32K-bit LDS
-//      filter; one whose two bits were both set already is a suspect (a
-//      repeated id, or an id whose bits other ids set).  Two bits instead
-//      of one cut these false suspects about six-fold at 2048 candidates;
+//   a. every candidate sets its three bits (in one word) of a 32K-bit LDS
+//      filter; one whose three bits were all set already is a suspect (a
+//      repeated id, or an id whose bits other ids set).  Three bits instead
+//      of one cut these false suspects about twenty-fold at 2048
+//      candidates (from ~64 to ~3), still with one LDS atomic per candidate;
 //   b. the suspects go into a small exact table, and a second pass counts
 //      every candidate that is in it.  A candidate not in it occurs exactly
 //      once: had its id occurred before, that earlier occurrence would have
@@ -883,11 +884,11 @@ __host__ __device__ inline uint32_t fast_lds_words(int L, uint32_t kmax) {
 }
 
 // One multiplicative hash per id serves all three structures: the filter
-// word is its top 10 bits and the word's two bits are bits 17..21 and
-// 12..16, the suspect table slot is its top 8 bits, and the suspects' filter
-// bit its top 13 (word = the slot, so one address reaches both).  An id that
-// shares a suspect's top bits costs at most a longer probe; results never
-// depend on the hash.  The multiply takes the
+// word is its top 10 bits and the word's three bits are bits 17..21, 12..16
+// and 7..11, the suspect table slot is its top 8 bits, and the suspects'
+// filter bit its top 13 (word = the slot, so one address reaches both).  An
+// id that shares a suspect's top bits costs at most a longer probe; results
+// never depend on the hash.  The multiply takes the
 // id's low 24 bits (a full-rate 24-bit multiply instead of a quarter-rate
 // 32-bit one): ids 2^24 apart share a hash, which costs the same.
 __device__ __forceinline__ uint32_t id_hash(uint32_t id) { return __umul24(id, 0x3779B1u); }
@@ -1088,7 +1089,7 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) idv[4 * u + i] = (room[u] > (uint32_t)i && vv[i] != self32) ? vv[i] : kEmpty;
       }
-      // 3a. filter: a candidate whose two bits are set already is a suspect.  The
+      // 3a. filter: a candidate whose three bits are set already is a suspect.  The
       // four atomics of a task are all issued before any result is used, so
       // they are waited for once (absent candidates take no part: a shared
       // word would serialise them).
@@ -1100,7 +1101,7 @@ __global__ __launch_bounds__(64, 5) void count_topk_fast_kernel(QueryArgs a) {
           for (int i = 0; i < 4; ++i) {
             const uint32_t x = idv[4 * u + i];
             const uint32_t h = id_hash(x);
-            bit[i] = (1u << ((h >> 17) & 31u)) | (1u << ((h >> 12) & 31u));
+            bit[i] = (1u << ((h >> 17) & 31u)) | (1u << ((h >> 12) & 31u)) | (1u << ((h >> 7) & 31u));
             old[i] = 0;
             if (x != kEmpty) old[i] = atomicOr(&bm[h >> 22], bit[i]);
           }
