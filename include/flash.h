@@ -65,6 +65,7 @@ extern "C" {
 #define FLASH_ENOSPC (-2)   /* workspace (or an output) too small */
 #define FLASH_EHIP (-3)     /* HIP runtime / launch error */
 #define FLASH_ENOTIMPL (-4) /* parameters outside what the kernels support */
+#define FLASH_ERANGE (-5)   /* a column id outside [0, n_cols) (flash_validate_csr) */
 
 /* Version of the index layout described above. */
 #define FLASH_INDEX_LAYOUT 2
@@ -122,6 +123,28 @@ FLASH_API int flash_index_layout(const flash_params *p, uint64_t *reservoirs, ui
  * query.  Unused sizes may be 0. */
 FLASH_API int flash_workspace_bytes(int op, const flash_params *p, int64_t n_rows,
                                     int64_t n_queries, int32_t k, size_t *bytes);
+
+/* Optional validation pass over a CSR batch.  The rows are subsets of
+ * {0, ..., D-1} (Sec. 2.1, D = n_cols); the hot-path calls neither check
+ * that nor need it (any int32 id is hashed, row pointers are clamped into
+ * [0, nnz]), so this pass is for callers that cannot vouch for their input.
+ * Clears the caller-owned device word *flags (uint32), then ORs into it
+ *   FLASH_CSR_BAD_COLUMN   a column id < 0 or >= n_cols;
+ *   FLASH_CSR_BAD_ROW_PTR  row_ptr[0] != 0, row_ptr[n_rows] != nnz, a row
+ *                          pointer outside [0, nnz], or one that decreases.
+ * Asynchronous on `stream` (no memset node: the clear is a fill kernel).
+ * Read *flags after the stream has synchronised and pass it to
+ * flash_csr_status.  row_ptr int64[n_rows + 1], col_idx int32[nnz], both
+ * device pointers; n_cols >= 1.  FLASH_EINVAL for bad sizes or NULL arrays. */
+#define FLASH_CSR_BAD_COLUMN 1u
+#define FLASH_CSR_BAD_ROW_PTR 2u
+FLASH_API int flash_validate_csr(int64_t n_rows, int64_t nnz, int64_t n_cols, const int64_t *row_ptr,
+                                 const int32_t *col_idx, uint32_t *flags, void *stream);
+
+/* Host only.  The status of a flags word written by flash_validate_csr:
+ * FLASH_EINVAL if the row pointers are malformed, else FLASH_ERANGE if a
+ * column is out of range, else FLASH_OK. */
+FLASH_API int flash_csr_status(uint32_t flags);
 
 /* Sec. 2.3 (DOPH) + Sec. 2.2 / Alg. 2 line 5 (MapKHashesToAddress).
  * For each CSR row i: the K*L densified one-permutation minhashes and the L

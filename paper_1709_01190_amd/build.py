@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libflash.so")
-SOURCES = ["doph_hash.hip", "reservoir_insert.hip", "count_topk.hip", "rerank.hip", "flash_capi.cpp"]
+SOURCES = ["doph_hash.hip", "reservoir_insert.hip", "count_topk.hip", "rerank.hip", "validate.hip",
+           "flash_capi.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = os.environ.get("FLASH_OFFLOAD_ARCH", "gfx950")
 

@@ -276,6 +276,24 @@ FLASH_API int flash_workspace_bytes(int op, const flash_params* p, int64_t n_row
   return FLASH_OK;
 }
 
+FLASH_API int flash_validate_csr(int64_t n_rows, int64_t nnz, int64_t n_cols, const int64_t* row_ptr,
+                                 const int32_t* col_idx, uint32_t* flags, void* stream) {
+  if (n_rows < 0) return fail(FLASH_EINVAL, "n_rows must be >= 0");
+  if (n_cols < 1) return fail(FLASH_EINVAL, "n_cols must be >= 1");
+  if (!row_ptr) return fail(FLASH_EINVAL, "row_ptr is NULL");
+  int r = check_csr(n_rows, nnz, row_ptr, col_idx);
+  if (r) return r;
+  if (!flags) return fail(FLASH_EINVAL, "flags is NULL");
+  hipError_t e = launch_validate_csr(n_rows, nnz, n_cols, row_ptr, col_idx, flags, (hipStream_t)stream);
+  return e == hipSuccess ? FLASH_OK : hip_fail(e, "validate_csr");
+}
+
+FLASH_API int flash_csr_status(uint32_t flags) {
+  if (flags & FLASH_CSR_BAD_ROW_PTR) return fail(FLASH_EINVAL, "malformed row pointers");
+  if (flags & FLASH_CSR_BAD_COLUMN) return fail(FLASH_ERANGE, "a column id is outside [0, n_cols)");
+  return FLASH_OK;
+}
+
 FLASH_API int flash_hash(const flash_params* p, int64_t n_rows, int64_t nnz, const int64_t* row_ptr,
                          const int32_t* col_idx, uint32_t* keys, uint32_t* codes, void* stream) {
   Cfg c;
@@ -718,6 +736,7 @@ FLASH_API const char* flash_strerror(int code) {
     case FLASH_ENOSPC: return "workspace or output too small";
     case FLASH_EHIP: return "HIP runtime error";
     case FLASH_ENOTIMPL: return "parameters outside the supported range";
+    case FLASH_ERANGE: return "column id out of range";
     default: return "unknown error";
   }
 }

@@ -97,6 +97,11 @@ hipError_t launch_rerank(int measure, int64_t n_indexed, int64_t nnz, const int6
                          const int32_t* q_col_idx, const int32_t* cand, int32_t n_cand, int32_t k,
                          int32_t* out_ids, int32_t* out_inter, hipStream_t s);
 
+// ---- CSR validation (validate.hip): clears *flags, then ORs the
+// FLASH_CSR_* bits of what it finds
+hipError_t launch_validate_csr(int64_t n_rows, int64_t nnz, int64_t n_cols, const int64_t* row_ptr,
+                               const int32_t* col_idx, uint32_t* flags, hipStream_t s);
+
 // ---- misc
 hipError_t launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t s);
 // p[i * stride] = v for i < n

@@ -21,6 +21,9 @@ FLASH_EINVAL = -1
 FLASH_ENOSPC = -2
 FLASH_EHIP = -3
 FLASH_ENOTIMPL = -4
+FLASH_ERANGE = -5
+FLASH_CSR_BAD_COLUMN = 1
+FLASH_CSR_BAD_ROW_PTR = 2
 EMPTY_KEY = 0xFFFFFFFF
 
 OP_HASH, OP_INSERT, OP_BUILD, OP_QUERY_KEYS, OP_QUERY, OP_KNN_GRAPH = range(6)
@@ -79,6 +82,8 @@ def lib():
         "flash_workspace_bytes": [ctypes.c_int, P, _I64, _I64, ctypes.c_int32,
                                   ctypes.POINTER(ctypes.c_size_t)],
         "flash_hash": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP],
+        "flash_validate_csr": [_I64, _I64, _I64, _VP, _VP, _VP, _VP],
+        "flash_csr_status": [ctypes.c_uint32],
         "flash_insert_keys": [P, _I64, _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_build_index": [P, _I64, _I64, _VP, _VP, _VP, _VP, _VP, ctypes.c_size_t, _VP],
         "flash_query_keys": [P, _VP, _I64, _I64, _VP, _VP, ctypes.c_int32, _VP, _VP, _VP,
@@ -186,6 +191,23 @@ def flash_version() -> str:
 
 
 # ------------------------------------------------------------------ device calls
+
+def flash_validate_csr(row_ptr, col_idx, n_cols, flags=None, stream=None) -> int:
+    """Runs the optional validation pass, waits for the device, and returns
+    FLASH_OK, FLASH_ERANGE (a column outside [0, n_cols)) or FLASH_EINVAL
+    (malformed row pointers).  flags: a one-element int32 device tensor to
+    use (else one is allocated)."""
+    n = row_ptr.numel() - 1
+    _need(row_ptr, n + 1, (torch.int64,), "row_ptr")
+    _need(col_idx, 0, (torch.int32,), "col_idx")
+    if flags is None:
+        flags = torch.empty(1, dtype=torch.int32, device=row_ptr.device)
+    _need(flags, 1, _U32, "flags")
+    _check(lib().flash_validate_csr(n, col_idx.numel(), int(n_cols), _p(row_ptr), _p(col_idx),
+                                    _p(flags), _s(stream)))
+    torch.cuda.synchronize(row_ptr.device)
+    return int(lib().flash_csr_status(int(flags.view(torch.int32).item()) & 0xFFFFFFFF))
+
 
 def flash_hash(p, row_ptr, col_idx, keys, codes=None, stream=None):
     n = row_ptr.numel() - 1

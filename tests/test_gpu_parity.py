@@ -181,6 +181,71 @@ def test_hash_malformed_row_pointers_stay_in_bounds(fl, orc):
     assert np.array_equal(k, orc.doph(orc.params(4, 16, 4, 8), wrp, wci))
 
 
+def csr_status_by_definition(fl, rp, ci, n_cols):
+    """The code flash_validate_csr must give, from the definitions (numpy)."""
+    nnz = ci.size
+    bad_rp = (rp.size == 0 or rp[0] != 0 or rp[-1] != nnz or bool((rp < 0).any()) or bool((rp > nnz).any())
+              or bool((np.diff(rp) < 0).any()))
+    bad_col = bool(((ci.astype(np.int64) < 0) | (ci.astype(np.int64) >= n_cols)).any())
+    return fl.FLASH_EINVAL if bad_rp else (fl.FLASH_ERANGE if bad_col else fl.FLASH_OK)
+
+
+def test_validate_csr(fl):
+    import torch
+    rng = np.random.default_rng(3)
+    n_cols = 1000
+    rows = [rng.integers(0, n_cols, size=int(s)).tolist() for s in rng.integers(0, 300, size=500)]
+    rp, ci = csr_from_rows(rows)
+    flags = torch.empty(1, dtype=torch.int32, device="cuda")
+
+    def check(rp, ci, n_cols, what):
+        want = csr_status_by_definition(fl, rp, ci, n_cols)
+        for off in range(4):   # the 16-byte body, the unaligned head and the tail all see every id
+            say("validate csr", what, "offset", off)
+            buf = torch.zeros(ci.size + 4, dtype=torch.int32, device="cuda")
+            if ci.size:
+                buf[off:off + ci.size] = torch.from_numpy(ci).cuda()
+            got = fl.flash_validate_csr(dev(rp), buf[off:off + ci.size], n_cols, flags=flags)
+            assert got == want, (what, off, got, want)
+        return want
+
+    assert check(rp, ci, n_cols, "valid") == fl.FLASH_OK
+    nnz = ci.size
+    for pos in (0, 1, 2, 3, nnz // 2, nnz - 4, nnz - 3, nnz - 2, nnz - 1):
+        for bad in (n_cols, -1, 1 << 30):
+            c2 = ci.copy()
+            c2[pos] = bad
+            assert check(rp, c2, n_cols, f"column {bad} at {pos}") == fl.FLASH_ERANGE
+    assert check(rp, ci, int(ci.max()), "n_cols = the largest id") == fl.FLASH_ERANGE
+    assert check(rp, ci, int(ci.max()) + 1, "n_cols = the largest id + 1") == fl.FLASH_OK
+    r2 = rp.copy()
+    r2[250] = r2[251] + 1   # decreases
+    assert check(r2, ci, n_cols, "decreasing row_ptr") == fl.FLASH_EINVAL
+    r3 = rp.copy()
+    r3[-1] -= 1             # does not end at nnz
+    assert check(r3, ci, n_cols, "row_ptr not ending at nnz") == fl.FLASH_EINVAL
+    r4 = rp.copy()
+    r4[0] = 1               # does not start at 0
+    assert check(r4, ci, n_cols, "row_ptr not starting at 0") == fl.FLASH_EINVAL
+    # both wrong: the row pointers decide
+    c5 = ci.copy()
+    c5[7] = -5
+    assert check(r2, c5, n_cols, "both") == fl.FLASH_EINVAL
+    # no rows, no columns
+    assert check(np.zeros(1, np.int64), np.zeros(0, np.int32), 5, "empty") == fl.FLASH_OK
+    # a large batch with one bad id far inside (many grid strides)
+    big = rng.integers(0, 1 << 20, size=6_000_003).astype(np.int32)
+    brp = np.array([0, 1_000_000, 6_000_003], dtype=np.int64)
+    assert check(brp, big, 1 << 20, "large valid") == fl.FLASH_OK
+    big[5_123_457] = 1 << 20
+    assert check(brp, big, 1 << 20, "large, one bad id") == fl.FLASH_ERANGE
+    # the hot path itself still takes any id: validation is optional
+    p = fl.flash_params.make(4, 16, 4, 32)
+    keys = torch.empty(2 * 16, dtype=torch.int32, device="cuda")
+    fl.flash_hash(p, dev(brp), dev(big), keys)
+    torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ insert
 
 def test_insert_tiny_workload(fl, orc):

@@ -103,6 +103,27 @@ def test_device_calls_reject_bad_arguments_before_launch(fl):
     assert b"n_queries" in L.flash_last_error()
 
 
+def test_csr_validation_status_and_host_checks(fl):
+    L = fl.lib()
+    # the status of a flags word: malformed row pointers first, then columns
+    assert L.flash_csr_status(0) == fl.FLASH_OK
+    assert L.flash_csr_status(fl.FLASH_CSR_BAD_COLUMN) == fl.FLASH_ERANGE
+    assert b"column" in L.flash_last_error()
+    assert L.flash_csr_status(fl.FLASH_CSR_BAD_ROW_PTR) == fl.FLASH_EINVAL
+    assert L.flash_csr_status(fl.FLASH_CSR_BAD_ROW_PTR | fl.FLASH_CSR_BAD_COLUMN) == fl.FLASH_EINVAL
+    assert L.flash_strerror(fl.FLASH_ERANGE) == b"column id out of range"
+    # argument errors return before anything touches the GPU
+    v = ctypes.c_void_p(16)
+    assert L.flash_validate_csr(10, 100, 0, v, v, v, None) == fl.FLASH_EINVAL      # n_cols < 1
+    assert b"n_cols" in L.flash_last_error()
+    assert L.flash_validate_csr(-1, 100, 5, v, v, v, None) == fl.FLASH_EINVAL      # n_rows < 0
+    assert L.flash_validate_csr(10, -1, 5, v, v, v, None) == fl.FLASH_EINVAL       # nnz < 0
+    assert L.flash_validate_csr(10, 100, 5, None, v, v, None) == fl.FLASH_EINVAL   # no row_ptr
+    assert L.flash_validate_csr(10, 100, 5, v, None, v, None) == fl.FLASH_EINVAL   # no col_idx
+    assert L.flash_validate_csr(10, 100, 5, v, v, None, None) == fl.FLASH_EINVAL   # no flags
+    assert b"flags" in L.flash_last_error()
+
+
 def test_binding_refuses_cpu_tensors(fl):
     import torch
     p = fl.flash_params.make(4, 16, 4, 32)
