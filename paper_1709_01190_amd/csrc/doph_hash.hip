@@ -2,15 +2,18 @@
 // keys of Sec. 2.2 ("MapKHashesToAddress"), one wavefront per CSR row.
 //
 // Per row the wave
-//   1. streams the row's column ids from HBM with 16-byte loads (scalar head
-//      and tail for the unaligned ends), hashes each id with the permutation
-//      pi(i) = fmix32(i ^ s_h), and keeps the minimum per bin with an LDS
-//      atomic min; bins are the B equal slices of the permuted range;
+//   1. reads the row's column ids (one per lane for rows of at most 256,
+//      else 16-byte loads with the unaligned ends one per lane), hashes each
+//      id with the permutation pi(i) = fmix32(i ^ s_h), and keeps the minimum
+//      per bin with an LDS atomic min; bins are the B equal slices of the
+//      permuted range;
 //   2. builds the occupancy bitmask with ballots (one 64-bit ballot per 64
-//      bins);
+//      bins) and, when B <= 256, an occupancy byte per bin;
 //   3. fills every empty bin from an originally occupied one: up to A probes
 //      at bins given by fmix32(((j << 16) | a) ^ s_d), then the nearest
-//      occupied bin to the right (cyclic);
+//      occupied bin to the right (cyclic).  The probe bins depend only on the
+//      bin and the seed, so when B <= 256 each lane keeps its bins' first
+//      eight as bytes in registers and tests them all at once;
 //   4. writes the L keys (K low-b-bit fields each) and, if asked, the B codes.
 // HBM traffic per row: 4 B per nonzero + 16 B of row_ptr + 4 L B of keys
 // (+ 4 B bytes of codes).
@@ -110,13 +113,29 @@ __device__ __forceinline__ ProbeTable make_probe_table(const HashArgs& a) {
 
 // Hashes one row with the whole wave.  LDS: mins[B] bin minima, occw[B/32]
 // occupancy bits; with PRE also occ8[256], one occupancy byte per bin.
+// row_ptr[next] and row_ptr[next + 1] (next >= 0), one per lane 0 and 1: a
+// vector load, so that waiting for the row's columns waits for it too.
+__device__ __forceinline__ int64_t load_row_bounds(const HashArgs& a, int64_t next) {
+  return next >= 0 ? a.row_ptr[next + (threadIdx.x & 1)] : 0;
+}
+
+// Lane l's value of a 64-bit register.
+__device__ __forceinline__ int64_t lane64(int64_t v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)((uint64_t)v >> 32), l);
+  return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Hashes row `row`, whose bounds (beg, end) were loaded a row ahead; loads
+// the bounds of row `next` (-1: none) into `bounds` before the row's columns.
 template <bool POW2, bool PRE>
-__device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_t* mins, uint32_t* occw,
-                                         uint8_t* occ8, const ProbeTable& pt, uint32_t& top_bin) {
+__device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, int64_t beg, int64_t end, int64_t next,
+                                         int64_t& bounds, uint32_t* mins, uint32_t* occw, uint8_t* occ8,
+                                         const ProbeTable& pt, uint32_t& top_bin) {
   const uint32_t lane = threadIdx.x;
   const int B = a.B;
   const int nwords = (B + 31) >> 5;
-  int64_t beg = a.row_ptr[row], end = a.row_ptr[row + 1];
+  bounds = load_row_bounds(a, next);
   beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
   end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
 
@@ -252,9 +271,10 @@ __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, uint32_
 
 // Static schedule: wave w hashes rows w, w + grid, ...  Dynamic schedule
 // (for batches of very uneven rows): each wave takes tiles of tile_rows
-// consecutive rows from a work counter until the tiles run out.
+// consecutive rows from a work counter until the tiles run out.  Launch
+// bounds for six waves per SIMD (at most 80 VGPRs).
 template <bool POW2, bool PRE>
-__global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
+__global__ __launch_bounds__(64, 6) void doph_hash_kernel(HashArgs a) {
   extern __shared__ uint32_t lds[];
   uint8_t* occ8 = reinterpret_cast<uint8_t*>(lds);  // [256] (PRE)
   uint32_t* mins = lds + (PRE ? kPreBins / 4 : 0);  // [B]
@@ -270,11 +290,20 @@ __global__ __launch_bounds__(64) void doph_hash_kernel(HashArgs a) {
       const int64_t r0 = (int64_t)t * a.tile_rows;
       if (r0 >= a.n_rows) break;
       const int64_t r1 = r0 + a.tile_rows < a.n_rows ? r0 + a.tile_rows : a.n_rows;
-      for (int64_t row = r0; row < r1; ++row) hash_row<POW2, PRE>(a, row, mins, occw, occ8, pt, top_bin);
+      int64_t bounds = load_row_bounds(a, r0);
+      for (int64_t row = r0; row < r1; ++row) {
+        const int64_t beg = lane64(bounds, 0), end = lane64(bounds, 1);
+        hash_row<POW2, PRE>(a, row, beg, end, row + 1 < r1 ? row + 1 : -1, bounds, mins, occw, occ8, pt, top_bin);
+      }
     }
   } else {
-    for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x)
-      hash_row<POW2, PRE>(a, row, mins, occw, occ8, pt, top_bin);
+    // each row's bounds are loaded while the row before it is hashed
+    int64_t bounds = load_row_bounds(a, blockIdx.x < a.n_rows ? (int64_t)blockIdx.x : -1);
+    for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) {
+      const int64_t beg = lane64(bounds, 0), end = lane64(bounds, 1);
+      const int64_t next = row + gridDim.x < a.n_rows ? row + gridDim.x : -1;
+      hash_row<POW2, PRE>(a, row, beg, end, next, bounds, mins, occw, occ8, pt, top_bin);
+    }
   }
 }
 
