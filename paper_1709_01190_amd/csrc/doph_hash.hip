@@ -126,16 +126,22 @@ __device__ __forceinline__ int64_t lane64(int64_t v, int l) {
   return (int64_t)(((uint64_t)hi << 32) | lo);
 }
 
-// Hashes row `row`, whose bounds (beg, end) were loaded a row ahead; loads
-// the bounds of row `next` (-1: none) into `bounds` before the row's columns.
-template <bool POW2, bool PRE>
+// Hashes row `row`.  PF: its bounds (beg, end) were loaded a row ahead, and
+// the bounds of row `next` (-1: none) are loaded into `bounds` before the
+// row's columns; else the row loads its own bounds first.
+template <bool POW2, bool PRE, bool PF>
 __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, int64_t beg, int64_t end, int64_t next,
                                          int64_t& bounds, uint32_t* mins, uint32_t* occw, uint8_t* occ8,
                                          const ProbeTable& pt, uint32_t& top_bin) {
   const uint32_t lane = threadIdx.x;
   const int B = a.B;
   const int nwords = (B + 31) >> 5;
-  bounds = load_row_bounds(a, next);
+  if (PF) {
+    bounds = load_row_bounds(a, next);
+  } else {
+    beg = a.row_ptr[row];
+    end = a.row_ptr[row + 1];
+  }
   beg = beg < 0 ? 0 : (beg > a.nnz ? a.nnz : beg);
   end = end < beg ? beg : (end > a.nnz ? a.nnz : end);
 
@@ -272,8 +278,10 @@ __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, int64_t
 // Static schedule: wave w hashes rows w, w + grid, ...  Dynamic schedule
 // (for batches of very uneven rows): each wave takes tiles of tile_rows
 // consecutive rows from a work counter until the tiles run out.  Launch
-// bounds for six waves per SIMD (at most 80 VGPRs).
-template <bool POW2, bool PRE>
+// bounds for six waves per SIMD (at most 80 VGPRs).  PF: row bounds loaded a
+// row ahead, which pays on long rows (their wait is not hidden by other work
+// of the row) and costs a few instructions per row on short ones.
+template <bool POW2, bool PRE, bool PF>
 __global__ __launch_bounds__(64, 6) void doph_hash_kernel(HashArgs a) {
   extern __shared__ uint32_t lds[];
   uint8_t* occ8 = reinterpret_cast<uint8_t*>(lds);  // [256] (PRE)
@@ -290,19 +298,19 @@ __global__ __launch_bounds__(64, 6) void doph_hash_kernel(HashArgs a) {
       const int64_t r0 = (int64_t)t * a.tile_rows;
       if (r0 >= a.n_rows) break;
       const int64_t r1 = r0 + a.tile_rows < a.n_rows ? r0 + a.tile_rows : a.n_rows;
-      int64_t bounds = load_row_bounds(a, r0);
+      int64_t bounds = PF ? load_row_bounds(a, r0) : 0;
       for (int64_t row = r0; row < r1; ++row) {
-        const int64_t beg = lane64(bounds, 0), end = lane64(bounds, 1);
-        hash_row<POW2, PRE>(a, row, beg, end, row + 1 < r1 ? row + 1 : -1, bounds, mins, occw, occ8, pt, top_bin);
+        const int64_t beg = PF ? lane64(bounds, 0) : 0, end = PF ? lane64(bounds, 1) : 0;
+        hash_row<POW2, PRE, PF>(a, row, beg, end, row + 1 < r1 ? row + 1 : -1, bounds, mins, occw, occ8, pt,
+                                top_bin);
       }
     }
   } else {
-    // each row's bounds are loaded while the row before it is hashed
-    int64_t bounds = load_row_bounds(a, blockIdx.x < a.n_rows ? (int64_t)blockIdx.x : -1);
+    int64_t bounds = PF ? load_row_bounds(a, blockIdx.x < a.n_rows ? (int64_t)blockIdx.x : -1) : 0;
     for (int64_t row = blockIdx.x; row < a.n_rows; row += gridDim.x) {
-      const int64_t beg = lane64(bounds, 0), end = lane64(bounds, 1);
+      const int64_t beg = PF ? lane64(bounds, 0) : 0, end = PF ? lane64(bounds, 1) : 0;
       const int64_t next = row + gridDim.x < a.n_rows ? row + gridDim.x : -1;
-      hash_row<POW2, PRE>(a, row, beg, end, next, bounds, mins, occw, occ8, pt, top_bin);
+      hash_row<POW2, PRE, PF>(a, row, beg, end, next, bounds, mins, occw, occ8, pt, top_bin);
     }
   }
 }
@@ -332,8 +340,14 @@ hipError_t launch_doph_hash(const Cfg& c, int64_t n_rows, int64_t nnz, const int
   a.shift = pow2 ? 32 - (31 - __builtin_clz((unsigned)c.B)) : 0;
   const bool pre = c.B <= kPreBins;
   const size_t lds = sizeof(uint32_t) * ((size_t)c.B + (size_t)((c.B + 31) / 32)) + (pre ? kPreBins : 0);
-  const void* kern = pow2 ? (pre ? (const void*)doph_hash_kernel<true, true> : (const void*)doph_hash_kernel<true, false>)
-                          : (pre ? (const void*)doph_hash_kernel<false, true> : (const void*)doph_hash_kernel<false, false>);
+  // row bounds a row ahead when the rows average at least 256 ids
+  const bool pf = nnz >= 256 * n_rows;
+  const void* const kernels[8] = {
+      (const void*)doph_hash_kernel<false, false, false>, (const void*)doph_hash_kernel<false, false, true>,
+      (const void*)doph_hash_kernel<false, true, false>,  (const void*)doph_hash_kernel<false, true, true>,
+      (const void*)doph_hash_kernel<true, false, false>,  (const void*)doph_hash_kernel<true, false, true>,
+      (const void*)doph_hash_kernel<true, true, false>,   (const void*)doph_hash_kernel<true, true, true>};
+  const void* kern = kernels[(pow2 ? 4 : 0) + (pre ? 2 : 0) + (pf ? 1 : 0)];
   // as many one-wave blocks as fit the chip at once: with the static stride
   // every block then starts at launch and no block runs behind the rest
   const int64_t want = (int64_t)device_info().cus * resident_blocks(kern, lds);
