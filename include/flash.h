@@ -304,7 +304,7 @@ typedef struct flash_tuning {
                                     1024..16384, rounded down to a power of two.  Default 2048 */
     int32_t query_cap2;          /* the same for the second stage; default 4096 */
     int32_t query_blocks_per_cu; /* one-wave workgroups per CU in the first stage, 1..1024;
-                                    default 256 */
+                                    default 512 */
     int32_t query_big_waves;     /* waves per workgroup that share one query in the last stage
                                     when its table has >= 8192 entries: 1, 4, 8 or 16; default 8 */
     int32_t hash_tile_rows;      /* flash_query_batch*: 0 = static row stride; else each wave

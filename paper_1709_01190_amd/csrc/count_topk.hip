@@ -1613,7 +1613,7 @@ hipError_t launch_query(const Cfg& c, const int32_t* index,
   const int nw = (last >= 8192 && tu.query_big_waves > 1) ? tu.query_big_waves : 1;
 
   const int cus = device_info().cus;
-  const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 256;
+  const int per_cu = tu.query_blocks_per_cu > 0 ? tu.query_blocks_per_cu : 512;
   // the filter stage goes first unless every query is sure to exceed it
   // (full buckets with more than its 2048 candidates)
   const bool filter = tu.query_filter != 0 && !(skip_small && full > kFastCap);

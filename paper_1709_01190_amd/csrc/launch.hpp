@@ -41,7 +41,7 @@ const Device& device_info();
 struct Tuning {
   int query_cap1 = 2048;          // first query stage's table entries (0: no such stage)
   int query_cap2 = 4096;          // second stage's (0: none)
-  int query_blocks_per_cu = 256;  // first-stage blocks per CU
+  int query_blocks_per_cu = 512;  // first-stage blocks per CU
   int query_big_waves = 8;        // waves per workgroup in a last stage of >= 8192 entries (1: one wave)
   int hash_tile_rows = 0;         // 0: static row stride; else rows per tile taken from a work counter
   int query_skip_full = 1;        // leave out stages too small for L * R candidates when buckets are full

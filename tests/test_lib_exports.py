@@ -137,7 +137,7 @@ def test_binding_refuses_cpu_tensors(fl):
 def test_tuning_is_checked_and_restorable(fl):
     fl.flash_set_tuning(None)
     d = fl.flash_get_tuning().as_dict()
-    assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 256,
+    assert d == {"query_cap1": 2048, "query_cap2": 4096, "query_blocks_per_cu": 512,
                  "query_big_waves": 8, "hash_tile_rows": 0, "query_skip_full": 1, "query_filter": 1}
     fl.flash_set_tuning(query_big_waves=16, hash_tile_rows=32, query_cap2=0)
     d2 = fl.flash_get_tuning().as_dict()
