@@ -237,7 +237,7 @@ __device__ __forceinline__ void hash_row(const HashArgs& a, int64_t row, int64_t
 #pragma unroll 1
     for (int r = 0; r < rounds; ++r) {
       const uint32_t j = (uint32_t)r * kWave + lane;
-      // this round's two table words (r is the same in every lane)
+      // the table words of bins r * 64 + lane (r is the same in every lane)
       const uint32_t w0 = r == 0 ? pt.w[0][0] : r == 1 ? pt.w[1][0] : r == 2 ? pt.w[2][0] : pt.w[3][0];
       const uint32_t w1 = r == 0 ? pt.w[0][1] : r == 1 ? pt.w[1][1] : r == 2 ? pt.w[2][1] : pt.w[3][1];
       if (j < (uint32_t)B && !((own >> r) & 1u)) {
